@@ -1,0 +1,584 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics (closed forms, dense definitions, invariants, brute force on tiny
+inputs, published generator outputs). None of these compare the oracle with
+itself or with the HIP library.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import oracle as O
+from paper_2505_13390_amd import workloads as W
+from tests.conftest import GOLDEN
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ---------------------------------------------------------------- helpers
+def single_body(rest, tets=None, edges=None, vol=None, alpha=None, inv_mass=None, dt=1 / 60,
+                gravity=(0.0, 0.0, 0.0)):
+    rest = np.asarray(rest, np.float64)
+    n = rest.shape[0]
+    tets = np.zeros((0, 4), np.int32) if tets is None else np.asarray(tets, np.int32)
+    edges = np.zeros((0, 2), np.int32) if edges is None else np.asarray(edges, np.int32)
+    vol = np.zeros(0, np.int32) if vol is None else np.asarray(vol, np.int32)
+    m = edges.shape[0] + vol.shape[0]
+    alpha = np.zeros(m) if alpha is None else np.asarray(alpha, np.float64)
+    inv_mass = np.ones(n) if inv_mass is None else np.asarray(inv_mass, np.float64)
+    return W.Workload(name="t", rest=rest, inv_mass=inv_mass, tets=tets, edges=edges,
+                      vol_tet=vol, alpha=alpha, dt=dt, gravity=gravity, x0=rest.copy(),
+                      v0=np.zeros_like(rest))
+
+
+def fd_jacobian(sim, pos, h=1e-6):
+    """Central finite differences of the oracle's constraint values."""
+    m = sim.m
+    n = pos.shape[0]
+    J = np.zeros((m, 3 * n))
+    for v in range(n):
+        for k in range(3):
+            p1 = pos.copy(); p1[v, k] += h
+            p0 = pos.copy(); p0[v, k] -= h
+            J[:, 3 * v + k] = (sim.constraints(p1)[0] - sim.constraints(p0)[0]) / (2 * h)
+    return J
+
+
+def grad_matrix(sim, w, g):
+    """Sparse J (m x 3N) from per-row gradients and the row -> vertex map."""
+    m = sim.m
+    J = np.zeros((m, 3 * w.n_verts))
+    for r in range(m):
+        vs = w.edges[r] if r < w.edges.shape[0] else w.tets[w.vol_tet[r - w.edges.shape[0]]]
+        for k, v in enumerate(vs):
+            J[r, 3 * v:3 * v + 3] += g[r, k]
+    return J
+
+
+def dense(rp, col, val, n=None):
+    n = rp.shape[0] - 1 if n is None else n
+    return sp.csr_matrix((val, col, rp), shape=(n, n)).toarray()
+
+
+# ------------------------------------------------------- random generator
+def test_splitmix64_published_outputs():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    for inp, out in rows:
+        assert O.splitmix64(int(inp, 16)) == int(out, 16)
+        assert int(W.splitmix64(np.uint64(int(inp, 16)))) == int(out, 16)
+
+
+def test_mix64_matches_input_generator_definition():
+    for seed, stream, i in [(0, 0, 0), (20250513, 3, 17), (5, 2, 2 ** 40 + 3)]:
+        assert O.mix64(seed, stream, i) == int(W.mix64(seed, stream, np.uint64(i)))
+
+
+# ------------------------------------------------------ constraints (Eq. 3)
+def test_edge_constraint_closed_form():
+    w = single_body([[0, 0, 0], [3, 4, 0]], edges=[[0, 1]])
+    s = O.Sim(w)
+    C, g = s.constraints(np.array([[0, 0, 0], [6, 8, 0.0]]))
+    assert C[0] == pytest.approx(5.0, abs=1e-15)        # |(6,8,0)| - 5
+    assert np.allclose(g[0, 0], [-0.6, -0.8, 0]) and np.allclose(g[0, 1], [0.6, 0.8, 0])
+    assert (g[0, 0] + g[0, 1] == 0).all()                # translation invariance, exact
+
+
+def test_volume_constraint_closed_form_unit_tet():
+    rest = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    w = single_body(rest, tets=[[0, 1, 2, 3]], vol=[0])
+    s = O.Sim(w)
+    C0, g = s.constraints(rest)
+    assert C0[0] == 0.0                                  # rest state: exactly zero
+    # scaled by 2: V = 8/6, C = 8/6 - 1/6 = 7/6
+    C2, _ = s.constraints(2 * rest)
+    assert C2[0] == pytest.approx(7 / 6, rel=1e-15)
+    # dV/dx_k = outward-area-normal / 3 ... for the unit right tet: axis vectors / 6
+    assert np.allclose(g[0, 1], [1 / 6, 0, 0]) and np.allclose(g[0, 2], [0, 1 / 6, 0])
+    assert np.allclose(g[0, 3], [0, 0, 1 / 6]) and np.allclose(g[0, 0], [-1 / 6] * 3)
+
+
+def test_gradients_match_finite_differences():
+    w = W.perturbed(W.tiny_beam(2, 1, 1, volumes=True), 0.05)
+    s = O.Sim(w)
+    C, g = s.constraints(w.x0)
+    J = grad_matrix(s, w, g)
+    Jfd = fd_jacobian(s, w.x0)
+    assert np.abs(J - Jfd).max() <= 1e-7 * max(1.0, np.abs(J).max())
+    # translation invariance of every row
+    for r in range(s.m):
+        tot = g[r].sum(axis=0)
+        assert np.abs(tot).max() <= 1e-15
+
+
+# ---------------------------------------------------- system matrix (Eq. 3)
+@pytest.mark.parametrize("dims,vols", [((1, 1, 1), False), ((2, 1, 1), True), ((1, 2, 1), True)])
+def test_matrix_equals_dense_definition(dims, vols):
+    """A = gradC M^-1 gradC^T + alpha/dt^2 with gradC from finite differences."""
+    w = W.perturbed(W.tiny_beam(*dims, volumes=vols, alpha_edge=1e-6, alpha_vol=3e-7), 0.03)
+    s = O.Sim(w)
+    val, b = s.assemble(w.x0)
+    rp, col = s.pattern()
+    A = dense(rp, col, val)
+    Jfd = fd_jacobian(s, w.x0)
+    Minv = np.repeat(w.inv_mass, 3)
+    Aref = Jfd @ np.diag(Minv) @ Jfd.T + np.diag(w.alpha / w.dt ** 2)
+    assert np.abs(A - Aref).max() <= 1e-6 * np.abs(Aref).max()
+    # exact gradients: per-entry assembly equals the dense triple product
+    C, g = s.constraints(w.x0)
+    J = grad_matrix(s, w, g)
+    Aex = J @ np.diag(Minv) @ J.T + np.diag(w.alpha / w.dt ** 2)
+    assert np.abs(A - Aex).max() <= 1e-14 * np.abs(Aex).max()
+    # pattern: rows sharing a vertex, explicit zeros kept
+    inc = (np.abs(grad_matrix(s, w, np.ones_like(g))) > 0).astype(float)
+    struct = (inc @ inc.T) > 0
+    pat = dense(rp, col, np.ones_like(val)) > 0
+    assert (struct == pat).all()
+    # b = -C - alpha~ lambda with lambda = 0
+    assert np.array_equal(b, -C)
+    # bitwise symmetric, SPD with lambda_min >= min alpha~
+    assert np.array_equal(A, A.T)
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() >= (w.alpha / w.dt ** 2).min() * (1 - 1e-9)
+    # Gershgorin bound on lambda_max
+    assert ev.max() <= (np.abs(A).sum(axis=1)).max() * (1 + 1e-12)
+
+
+def test_distance_only_diagonal_is_constant():
+    """Sec. 4.2: with distance constraints the diagonal of A does not change."""
+    w = W.tiny_beam(3, 2, 2, volumes=False, alpha_edge=1e-8)
+    s = O.Sim(w)
+    rp, col = s.pattern()
+    v0, _ = s.assemble(w.rest)
+    v1, _ = s.assemble(W.perturbed(w, 0.05).x0)
+    diag = np.repeat(np.arange(s.m), np.diff(rp)) == col
+    assert np.allclose(v0[diag], v1[diag], rtol=1e-14, atol=0)
+    assert not np.allclose(v0[~diag], v1[~diag], rtol=1e-6)
+
+
+def test_pinned_shared_vertex_gives_explicit_zero():
+    w = W.tiny_beam(1, 1, 1, volumes=False)
+    s = O.Sim(w)
+    rp, col = s.pattern()
+    val, _ = s.assemble(w.rest)
+    rows = np.repeat(np.arange(s.m), np.diff(rp))
+    pinned = set(np.nonzero(w.inv_mass == 0)[0])
+    # entries whose only shared vertex is pinned are stored and exactly 0
+    zeros = 0
+    for e in range(len(col)):
+        r, c = rows[e], col[e]
+        if r == c:
+            continue
+        shared = set(w.edges[r]) & set(w.edges[c])
+        if shared <= pinned:
+            assert val[e] == 0.0
+            zeros += 1
+    assert zeros > 0
+
+
+# --------------------------------------------------------- rest state etc.
+def test_rest_state_is_a_fixed_point():
+    w = W.tiny_beam(3, 1, 1, volumes=True)
+    w.gravity = (0.0, 0.0, 0.0)
+    s = O.Sim(w)
+    pos, vel = O.positions(w)
+    x_before = pos.copy()
+    r = s.step(pos, vel, 3)
+    assert r["status"] == 0
+    assert np.array_equal(pos, x_before) and not vel.any()
+    assert (r["bnorm"] == 0).all() and (r["pcg_iters"] == 0).all()
+    assert not s.lam().any()
+
+
+def test_single_constraint_is_xpbd_update():
+    """Eq. 4: with one row, dlambda = b / A_11 (the XPBD local update)."""
+    w = single_body([[0, 0, 0], [1, 0, 0]], edges=[[0, 1]], alpha=[1e-4],
+                    inv_mass=[0.5, 2.0])
+    s = O.Sim(w)
+    x = np.array([[0, 0, 0], [1.3, 0.1, 0.0]])
+    val, b = s.assemble(x)
+    h = O.Hier.build(np.array([0, 1]), np.array([0], np.int32), val)
+    dl, st = h.pcg(b, 1e-12)
+    assert dl[0] == pytest.approx(b[0] / val[0], rel=1e-15)
+    assert val[0] == pytest.approx(2.5 + 1e-4 * 3600, rel=1e-15)
+
+
+def test_disjoint_springs_equal_xpbd():
+    """Diagonal A (no shared vertices): the global solve equals XPBD's."""
+    n = 20
+    rest = np.zeros((2 * n, 3)); rest[1::2, 0] = 1.0; rest[:, 1] = np.repeat(np.arange(n), 2)
+    edges = np.stack([np.arange(0, 2 * n, 2), np.arange(1, 2 * n, 2)], 1)
+    w = single_body(rest, edges=edges, alpha=np.full(n, 1e-5))
+    s = O.Sim(w)
+    x = W.perturbed(w, 0.1).x0
+    val, b = s.assemble(x)
+    rp, col = s.pattern()
+    assert np.array_equal(np.diff(rp), np.ones(n))
+    h = O.Hier.build(rp, col, val)
+    dl, st = h.pcg(b, 1e-12)
+    assert np.allclose(dl, b / val, rtol=1e-14, atol=0)
+
+
+def test_two_particle_spring_hard_constraint_one_newton_step():
+    w = single_body([[0, 0, 0], [1, 0, 0]], edges=[[0, 1]], alpha=[0.0])
+    w.x0 = np.array([[0.1, 0.2, 0.0], [1.5, -0.3, 0.4]])
+    opts = O.default_opts(omega_relax=1.0)
+    s = O.Sim(w, opts)
+    pos, vel = O.positions(w)
+    s.step(pos, vel, 1)
+    assert np.linalg.norm(pos[1] - pos[0]) == pytest.approx(1.0, rel=1e-14)
+
+
+def test_single_tet_volume_newton_converges_quadratically():
+    rest = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    w = single_body(rest, tets=[[0, 1, 2, 3]], vol=[0], alpha=[0.0])
+    w.x0 = rest * np.array([1.3, 1.2, 1.25]) + 0.02
+    s = O.Sim(w, O.default_opts(omega_relax=1.0))
+    errs = []
+    pos, vel = O.positions(w)
+    for it in range(4):
+        C, _ = s.constraints(pos)
+        errs.append(abs(C[0]))
+        s.step(pos, vel, 1)
+        vel[:] = 0
+    assert errs[1] < errs[0] * 0.5
+    for k in range(1, 3):
+        if errs[k + 1] > 1e-15:
+            assert errs[k + 1] <= 50 * errs[k] ** 2
+
+
+def test_momentum_conserved_free_body():
+    w = W.tiny_beam(3, 2, 2, volumes=True, pin=False, alpha_edge=1e-7, alpha_vol=1e-7)
+    w.gravity = (0.0, 0.0, 0.0)
+    w = W.perturbed(w, 0.02)
+    w.inv_mass = np.linspace(0.5, 2.0, w.n_verts)
+    s = O.Sim(w)
+    pos, vel = O.positions(w)
+    mass = 1 / w.inv_mass
+    p0 = (mass[:, None] * pos).sum(0)
+    s.step(pos, vel, 3)
+    p1 = (mass[:, None] * pos).sum(0)
+    assert np.abs(p1 - p0).max() <= 1e-13 * np.abs(p0).max()
+    assert np.abs((mass[:, None] * vel).sum(0)).max() <= 1e-11
+
+
+# --------------------------------------------------------------- PCG
+def test_cg_terminates_in_n_steps_small():
+    rng = np.random.default_rng(1)
+    for n in [5, 12, 25]:
+        M = rng.standard_normal((n, n))
+        A = M @ M.T + n * np.eye(n)
+        As = sp.csr_matrix(A)
+        h = O.Hier.build(As.indptr.astype(np.int64), As.indices, As.data,
+                         O.default_opts(coarse_max=0, dense_max=0, max_levels=1))
+        b = rng.standard_normal(n)
+        x, st = h.pcg(b, 1e-10, 10 * n, precond=False)
+        assert st["status"] == 0 and st["iters"] <= n
+        assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-12)
+
+
+def test_direct_coarsest_single_level_converges_in_one_iteration():
+    w = W.perturbed(W.tiny_beam(3, 2, 2, volumes=True), 0.02)
+    s = O.Sim(w)
+    val, b = s.assemble(w.x0)
+    rp, col = s.pattern()
+    assert s.m <= 400
+    h = O.Hier.build(rp, col, val)
+    assert h.levels == 1 and h.last_dense
+    x, st = h.pcg(b, 1e-6)
+    assert st["iters"] == 1
+    A = dense(rp, col, val)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-14 * np.abs(x).max())
+
+
+def small_hier(dims=(6, 3, 3), vols=True, **kw):
+    w = W.perturbed(W.tiny_beam(*dims, volumes=vols, alpha_edge=1e-7, alpha_vol=1e-8), 0.01)
+    s = O.Sim(w)
+    val, b = s.assemble(w.x0)
+    rp, col = s.pattern()
+    opts = O.default_opts(coarse_max=kw.pop("coarse_max", 30), **kw)
+    return w, s, rp, col, val, b, O.Hier.build(rp, col, val, opts)
+
+
+def test_mgpcg_matches_dense_direct_solve():
+    w, s, rp, col, val, b, h = small_hier()
+    assert h.levels >= 2
+    x, st = h.pcg(b, 1e-10, 2000)
+    A = dense(rp, col, val)
+    xd = np.linalg.solve(A, b)
+    assert st["status"] == 0
+    assert np.linalg.norm(A @ x - b) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.cond(A) * np.linalg.norm(xd)
+
+
+def test_vcycle_symmetric_positive():
+    w, s, rp, col, val, b, h = small_hier()
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        y, z = rng.standard_normal((2, s.m))
+        a1, a2 = z @ h.vcycle(y), y @ h.vcycle(z)
+        assert abs(a1 - a2) <= 1e-13 * (abs(a1) + abs(a2))
+        assert y @ h.vcycle(y) > 0
+
+
+def test_vcycle_reduces_to_exact_solve_on_one_level():
+    w, s, rp, col, val, b, h = small_hier(coarse_max=10000)
+    A = dense(rp, col, val)
+    assert h.levels == 1
+    r = np.random.default_rng(0).standard_normal(s.m)
+    assert np.allclose(h.vcycle(r), np.linalg.solve(A, r), rtol=1e-10,
+                       atol=1e-12 * np.abs(np.linalg.solve(A, r)).max())
+
+
+def test_amg_is_effective_on_poisson():
+    """Sanity of the whole setup + V-cycle: far fewer iterations than CG."""
+    n = 64
+    T = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(n, n))
+    A = (sp.kron(sp.eye(n), T) + sp.kron(T, sp.eye(n))).tocsr()
+    A.sort_indices()
+    h = O.Hier.build(A.indptr.astype(np.int64), A.indices, A.data, O.default_opts())
+    b = np.random.default_rng(0).standard_normal(n * n)
+    _, st_mg = h.pcg(b, 1e-8, 1000)
+    _, st_cg = h.pcg(b, 1e-8, 5000, precond=False)
+    assert st_mg["status"] == 0 and st_mg["iters"] * 4 < st_cg["iters"]
+
+
+# -------------------------------------------------------- setup pieces
+def test_galerkin_equals_dense_triple_product():
+    w, s, rp, col, val, b, h = small_hier()
+    for l in range(h.levels - 1):
+        rpl, coll, vall = h.matrix(l)
+        agg, p, B = h.transfer(l)
+        rpc, colc, valc = h.matrix(l + 1)
+        nc = rpc.shape[0] - 1
+        P = np.zeros((rpl.shape[0] - 1, nc))
+        idx = np.nonzero(agg >= 0)[0]
+        P[idx, agg[idx]] = p[idx]
+        Ac = dense(rpc, colc, valc, nc)
+        ref = P.T @ dense(rpl, coll, vall) @ P
+        assert np.abs(Ac - ref).max() <= 1e-14 * np.abs(ref).max()
+        # P^T P = I (disjoint supports, unit columns)
+        assert np.allclose(P.T @ P, np.eye(nc), atol=1e-15 * 10)
+        # the next-level candidate reproduces this level's: P B_{l+1} = B_l
+        if l + 1 < h.levels - 1:
+            _, _, Bn = h.transfer(l + 1)
+            assert np.allclose((P @ Bn)[idx], B[idx], rtol=1e-14, atol=0)
+        assert np.array_equal(Ac, Ac.T)
+        assert np.linalg.eigvalsh(Ac).min() > 0
+
+
+def test_piecewise_constant_candidate_mode():
+    w, s, rp, col, val, b, h = small_hier(b_mode=1)
+    agg, p, B = h.transfer(0)
+    for a in range(agg.max() + 1):
+        members = agg == a
+        assert np.allclose(p[members], 1 / np.sqrt(members.sum()), rtol=1e-15)
+
+
+def test_omega_from_power_method_bounds_lambda_max():
+    w, s, rp, col, val, b, h = small_hier()
+    for l in range(h.levels - (1 if h.last_dense else 0)):
+        rpl, coll, vall = h.matrix(l)
+        A = dense(rpl, coll, vall)
+        d = np.diag(A)
+        lam = np.linalg.eigvalsh(A / np.sqrt(np.outer(d, d))).max()
+        est = 2 / h.info(l)["omega"] - 0.1
+        assert est <= lam * (1 + 1e-12)
+        assert est >= 0.95 * lam
+
+
+def chain(n):
+    T = sp.diags([-1.0, 2.0, -1.0], [-1, 0, 1], shape=(n, n)).tocsr()
+    T.sort_indices()
+    return T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data
+
+
+def test_aggregation_chain_textbook():
+    rp, col, val = chain(11)
+    prio = np.arange(11)[::-1].astype(np.uint64)       # visit 0, 1, 2, ...
+    agg, na = O.aggregate(rp, col, val, prio)
+    assert agg.tolist() == [0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3]
+    assert na == 4
+
+
+def test_strength_threshold_kept_on_equality():
+    # theta = 0.5 is exact in binary: a_01^2 = 1 == 0.25 * 4 * 1 -> strong
+    A = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 1.0]]))
+    agg, na = O.aggregate(A.indptr.astype(np.int64), A.indices, A.data,
+                          np.array([2, 1], np.uint64), theta=0.5)
+    assert agg.tolist() == [0, 0]
+    A = sp.csr_matrix(np.array([[4.0, 0.999], [0.999, 1.0]]))
+    agg, na = O.aggregate(A.indptr.astype(np.int64), A.indices, A.data,
+                          np.array([2, 1], np.uint64), theta=0.5)
+    assert agg.tolist() == [-1, -1] and na == 0
+
+
+def random_graph(n, p, rng):
+    M = (rng.random((n, n)) < p).astype(float)
+    M = np.triu(M, 1)
+    M = M + M.T
+    W_ = M * rng.uniform(0.5, 2.0, (n, n))
+    W_ = np.triu(W_, 1); W_ = W_ + W_.T
+    A = -W_ + np.diag(W_.sum(1) + 1.0)
+    As = sp.csr_matrix(A)
+    As.sort_indices()
+    return A, As
+
+
+def test_aggregation_properties_brute_force():
+    """Pass 1 is the greedy distance-2 independent set in priority order: a set
+    R is that set iff no two members lie within distance 2 and every other
+    connected node has a member of higher priority within distance 2. Checked
+    by enumeration on random graphs, with the rest of Sec. 4.1's rules."""
+    rng = np.random.default_rng(11)
+    for trial in range(150):
+        n = int(rng.integers(2, 30))
+        A, As = random_graph(n, float(rng.uniform(0.05, 0.4)), rng)
+        prio = rng.permutation(n).astype(np.uint64)
+        agg, na, root = O.aggregate(As.indptr.astype(np.int64), As.indices, As.data, prio,
+                                    with_roots=True)
+        d = np.diag(A)
+        S = (A * A >= 0.01 * np.outer(d, d)) & ~np.eye(n, dtype=bool)
+        conn = S.any(1)
+        S1 = S | np.eye(n, dtype=bool)
+        D2 = (S1.astype(int) @ S1.astype(int)) > 0          # distance <= 2
+        assert ((agg >= 0) == conn).all()                    # isolated nodes stay alone
+        R = np.nonzero(root)[0]
+        assert conn[R].all()
+        for a in R:                                           # independence
+            for b in R:
+                assert a == b or not D2[a, b]
+        for v in np.nonzero(conn & ~root)[0]:                 # domination by priority
+            assert any(D2[v, u] and prio[u] > prio[v] for u in R)
+        assert len(R) == na
+        for a, r in enumerate(R):                             # numbered by root index
+            assert agg[r] == a
+            assert (agg[np.nonzero(S[r])[0]] == a).all()      # root + strong neighbours
+        p1 = np.full(n, -1)
+        for a, r in enumerate(R):
+            p1[r] = a
+            p1[np.nonzero(S[r])[0]] = a
+        for i in range(n):                                    # pass 2: strongest neighbour
+            if conn[i] and p1[i] < 0:
+                nb = [j for j in np.nonzero(S[i])[0] if p1[j] >= 0]
+                assert nb
+                best = max(nb, key=lambda j: (abs(A[i, j]), -j))
+                assert agg[i] == p1[best]
+        for a in range(na):                                   # aggregates connected in S
+            mem = set(np.nonzero(agg == a)[0])
+            seen = {min(mem)}
+            stack = [min(mem)]
+            while stack:
+                u = stack.pop()
+                for v in np.nonzero(S[u])[0]:
+                    if v in mem and v not in seen:
+                        seen.add(v); stack.append(v)
+            assert seen == mem
+
+
+def test_greedy_colouring_characterisation():
+    rng = np.random.default_rng(5)
+    for trial in range(100):
+        n = int(rng.integers(2, 40))
+        A, As = random_graph(n, float(rng.uniform(0.05, 0.5)), rng)
+        prio = rng.permutation(n).astype(np.uint64)
+        c, nc = O.color(As.indptr.astype(np.int64), As.indices, prio)
+        adj = (A != 0) & ~np.eye(n, dtype=bool)
+        for i in range(n):
+            nb = np.nonzero(adj[i])[0]
+            assert (c[nb] != c[i]).all()
+            higher = {c[j] for j in nb if prio[j] > prio[i]}
+            assert c[i] == min(set(range(n + 1)) - higher)
+        assert nc == c.max() + 1
+
+
+def test_near_kernel_sweeps_lower_the_rayleigh_quotient():
+    """Sec. 4.3: GS sweeps on A x = 0 damp the high-energy components."""
+    w, s, rp, col, val, b, _ = small_hier()
+    A = dense(rp, col, val)
+    rq = []
+    for sweeps in [0, 1, 5, 20]:
+        h = O.Hier.build(rp, col, val, O.default_opts(coarse_max=30, gs_sweeps=sweeps))
+        _, _, B = h.transfer(0)
+        rq.append(B @ A @ B / (B @ B))
+    assert rq[0] > rq[1] > rq[2] > rq[3]
+    # x0 lies in (0, max|A_ij|)
+    h0 = O.Hier.build(rp, col, val, O.default_opts(coarse_max=30, gs_sweeps=0))
+    B0 = h0.transfer(0)[2]
+    assert (B0 > 0).all() and (B0 < np.abs(val).max()).all()
+
+
+def test_one_gs_sweep_zeroes_the_last_colour_residual():
+    w, s, rp, col, val, b, _ = small_hier()
+    A = dense(rp, col, val)
+    h = O.Hier.build(rp, col, val, O.default_opts(coarse_max=30, gs_sweeps=1))
+    c, nc = h.colors()
+    B = h.transfer(0)[2]
+    last = c == nc - 1
+    assert np.abs((A @ B)[last]).max() <= 1e-12 * np.abs(A).max() * np.abs(B).max()
+
+
+def test_gs_sweep_does_not_increase_energy_norm():
+    w, s, rp, col, val, b, _ = small_hier()
+    A = dense(rp, col, val)
+    prev = None
+    for sweeps in range(0, 6):
+        h = O.Hier.build(rp, col, val, O.default_opts(coarse_max=30, gs_sweeps=sweeps))
+        B = h.transfer(0)[2]
+        e = B @ A @ B
+        if prev is not None:
+            assert e <= prev * (1 + 1e-12)
+        prev = e
+
+
+# --------------------------------------------------------- lazy setup
+def test_lazy_setup_schedule():
+    w = W.perturbed(W.tiny_beam(8, 3, 3, volumes=True), 0.01)
+    s = O.Sim(w, O.default_opts(coarse_max=40, reuse_interval=2))
+    pos, vel = O.positions(w)
+    flags = []
+    for f in range(4):
+        flags.append(s.step(pos, vel, 3)["setup"].tolist())
+    assert flags == [[1, 0, 0], [0, 0, 0], [1, 0, 0], [0, 0, 0]]
+    s = O.Sim(w, O.default_opts(coarse_max=40, reuse_interval=0))
+    pos, vel = O.positions(w)
+    assert s.step(pos, vel, 3)["setup"].tolist() == [1, 1, 1]
+
+
+# ------------------------------------------------------------ errors
+def test_create_rejects_bad_input():
+    rest = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    with pytest.raises(O.OracleError):
+        O.Sim(single_body(rest, edges=[[0, 1]], alpha=[-1.0]))
+    with pytest.raises(O.OracleError):
+        O.Sim(single_body(rest, edges=[[1, 0]]))
+    with pytest.raises(O.OracleError):
+        O.Sim(single_body(rest, tets=[[0, 2, 1, 3]], vol=[0]))      # inverted
+    with pytest.raises(O.OracleError):
+        O.Sim(single_body(np.zeros((2, 3)), edges=[[0, 1]]))        # zero length
+    w = single_body(rest, edges=[[0, 1]])
+    w.dt = 0.0
+    with pytest.raises(O.OracleError):
+        O.Sim(w)
+
+
+def test_step_rejects_nan_and_keeps_state():
+    w = W.tiny_beam(2, 1, 1)
+    s = O.Sim(w)
+    pos, vel = O.positions(w)
+    pos[3, 1] = np.nan
+    keep = pos.copy()
+    assert s.step(pos, vel, 2)["status"] == O.E_INVALID
+    assert np.array_equal(np.isnan(pos), np.isnan(keep)) and np.array_equal(
+        pos[~np.isnan(pos)], keep[~np.isnan(keep)])
+
+
+def test_indefinite_matrix_breaks_down():
+    A = sp.csr_matrix(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    h = O.Hier.build(A.indptr.astype(np.int64), A.indices, A.data,
+                     O.default_opts(coarse_max=0, dense_max=0, max_levels=1))
+    _, st = h.pcg(np.array([1.0, -1.0]), 1e-10, 10, precond=False)
+    assert st["status"] == O.E_BREAKDOWN
+    with pytest.raises(O.OracleError):
+        O.Hier.build(A.indptr.astype(np.int64), A.indices, A.data)  # dense factor fails
