@@ -70,7 +70,7 @@ typedef struct orc_opts {
   int power_iters;     /* power-method iterations for lambda_max: 30 */
   double omega_relax;  /* x += omega dx (Algorithm 1): 0.1 */
   double tol;          /* PCG relative residual: 1e-6 */
-  int max_pcg;         /* PCG iteration cap: 200 */
+  int max_pcg;         /* PCG iteration cap: 1000 */
   uint64_t seed;       /* solver's own random streams */
   int reuse_interval;  /* setup at iteration 0 of frames f % R == 0; 0 = every iteration */
   int b_mode;          /* 0 = smoothed near-kernel, 1 = all-ones candidate */
@@ -91,7 +91,7 @@ void orc_default_opts(orc_opts *o) {
   o->power_iters = 30;
   o->omega_relax = 0.1;
   o->tol = 1e-6;
-  o->max_pcg = 200;
+  o->max_pcg = 1000;
   o->seed = 20250513ULL;
   o->reuse_interval = 20;
   o->b_mode = 0;
@@ -185,6 +185,7 @@ typedef struct {
   int32_t *vc_row, *vc_slot;
   /* state */
   double *lambda, *C, *grad; /* grad[m][4][3] */
+  double *b_last;            /* right-hand side of the last global iteration */
   int64_t frame;
   void *hier;
 } orc_sim;
@@ -324,8 +325,9 @@ orc_sim *orc_sim_create(int64_t n_verts, const double *rest, const double *inv_m
   s->lambda = calloc(m ? m : 1, sizeof(double));
   s->C = calloc(m ? m : 1, sizeof(double));
   s->grad = calloc(12 * (m ? m : 1), sizeof(double));
+  s->b_last = calloc(m ? m : 1, sizeof(double));
   if (!s->rest || !s->w || !s->tets || !s->rv || !s->rk || !s->rest_c || !s->alpha_t ||
-      !s->lambda || !s->C || !s->grad) { orc_sim_free(s); *status = ORC_E_NOMEM; return NULL; }
+      !s->lambda || !s->C || !s->grad || !s->b_last) { orc_sim_free(s); *status = ORC_E_NOMEM; return NULL; }
   memcpy(s->rest, rest, sizeof(double) * 3 * n_verts);
   memcpy(s->w, inv_mass, sizeof(double) * n_verts);
   if (n_tets) memcpy(s->tets, tets, sizeof(int32_t) * 4 * n_tets);
@@ -1064,7 +1066,7 @@ done:
 void orc_sim_free(orc_sim *s) {
   if (!s) return;
   free(s->rest); free(s->w); free(s->tets); free(s->rv); free(s->rk); free(s->rest_c);
-  free(s->alpha_t); free(s->lambda); free(s->C); free(s->grad);
+  free(s->alpha_t); free(s->lambda); free(s->C); free(s->grad); free(s->b_last);
   free(s->vc_ptr); free(s->vc_row); free(s->vc_slot);
   csr_free(&s->A);
   orc_hier_free((hier_t *)s->hier);
@@ -1078,6 +1080,7 @@ void orc_sim_get_matrix_values(const orc_sim *s, double *val) {
   memcpy(val, s->A.val, sizeof(double) * s->A.nnz);
 }
 void orc_sim_set_frame(orc_sim *s, int64_t f) { s->frame = f; }
+void orc_sim_get_rhs(const orc_sim *s, double *b) { memcpy(b, s->b_last, sizeof(double) * s->m); }
 void orc_sim_invalidate(orc_sim *s) { orc_hier_free((hier_t *)s->hier); s->hier = NULL; }
 
 /* pos[N][3], vel[N][3] in/out. Per iteration outputs (nullable, length
@@ -1109,6 +1112,7 @@ int orc_sim_step(orc_sim *s, double *pos, double *vel, int n_iters, double *bnor
     assemble(s, s->A.val, b);
     double bn = sqrt(dot(m, b, b));
     if (bnorm_out) bnorm_out[ite] = bn;
+    memcpy(s->b_last, b, sizeof(double) * m);
     int R = s->o.reuse_interval;
     int due = (s->hier == NULL) || (R <= 0) || (ite == 0 && (s->frame % R) == 0);
     if (setup_out) setup_out[ite] = due;

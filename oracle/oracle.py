@@ -69,6 +69,7 @@ def lib():
         L.orc_sim_get_lambda.argtypes = [P, P]
         L.orc_sim_get_matrix_values.argtypes = [P, P]
         L.orc_sim_set_frame.argtypes = [P, C.c_int64]
+        L.orc_sim_get_rhs.argtypes = [P, P]
         L.orc_sim_invalidate.argtypes = [P]
         L.orc_hier_build.restype = P
         L.orc_hier_build.argtypes = [C.c_int64, P, P, P, C.POINTER(Opts), C.POINTER(C.c_int)]
@@ -282,6 +283,11 @@ class Sim:
     def matrix_values(self):
         out = np.zeros(self.nnz)
         lib().orc_sim_get_matrix_values(self.s, _p(out))
+        return out
+
+    def rhs(self):
+        out = np.zeros(self.m)
+        lib().orc_sim_get_rhs(self.s, _p(out))
         return out
 
     def set_frame(self, f: int):
