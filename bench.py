@@ -1,0 +1,151 @@
+"""Benchmark of the MGPBD global iteration on one MI355X.
+
+One step = one frame of Algorithm 1 (predict, 20 global iterations of
+assemble -> lazy AMG setup -> Galerkin -> MGPCG to 1e-6 -> update, velocity)
+on the 32x32x128-cube tetrahedral beam with edge and volume constraints
+(1,731,776 constraint rows, 155,246,662 entries of A), FP64, lazy setup
+every 20 frames. Prints one JSON line.
+
+value = PCG throughput: sum over solves of (rows x PCG iterations) divided by
+the time spent in the PCG loops (V-cycles included; assembly, Galerkin and
+setup excluded). ms_per_step = wall time per frame.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("ms/frame and PCG constraint-DOF·iters/s at 1e-6 rel residual; "
+          "SpMV HBM GB/s")
+PEAK_HBM_GBS = 8000.0
+
+
+def spmv_bytes(m: int, nnz: int) -> int:
+    """Algorithmic bytes of one fine-level A p product (FP64 CSR, int32
+    columns, int64 row pointers): values + columns + row pointers + one read
+    of p + one write of q."""
+    return 12 * nnz + 8 * (m + 1) + 8 * m + 8 * m
+
+
+def cpu_baseline(w, seconds_hint: float = 20.0):
+    """The FP64 oracle on the same workload: frame 0, global iteration 0,
+    a fixed number of preconditioned CG iterations (setup not timed)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    sim = O.Sim(w)
+    pos, vel = O.positions(w)
+    # semi-implicit Euler predict of frame 0 (what the first global iteration sees)
+    free = w.inv_mass > 0
+    g = np.asarray(w.gravity)
+    vel[free] += w.dt * g
+    pos[free] += w.dt * vel[free]
+    val, b = sim.assemble(pos)
+    rp, col = sim.pattern()
+    h = O.Hier.build(rp, col, val)
+    iters = 10
+    t0 = time.perf_counter()
+    _, st = h.pcg(b, 1e-6, 1000, force_iters=iters)
+    dt = time.perf_counter() - t0
+    return {"value": w.n_rows * st["iters"] / dt, "unit": "constraint-DOF*iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%s, frame 0 global iteration 0: %d MGPCG iterations of the single-thread "
+                      "FP64 oracle (%.1f s; setup and assembly untimed)"
+                      % (w.name, st["iters"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--reuse", type=int, default=20)
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU layout of this solver is a design "
+              "note (instances or slabs per GPU), no figure at several GPUs is produced.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_13390_amd import binding as B
+    from paper_2505_13390_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.CONFIGS[args.config]()
+    n_iters = args.iters or w.iters
+    prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
+    opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
+                                  profile_spmv=0 if args.no_profile else 1)
+    t0 = time.perf_counter()
+    body = B.Body(w, opt)
+    print("created %s: %d rows, %d entries in %.1f s" % (w.name, body.m, body.nnz,
+                                                         time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    for f in range(args.warmup):
+        r = body.step(n_iters)
+        print("warmup frame %d: %.1f ms, pcg iters %s" % (f, r["ms_total"], r["pcg_iters"].tolist()),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for f in range(args.steps):
+        res.append(body.step(n_iters))
+        print("frame %d: %.1f ms, setup %.1f ms, pcg %.1f ms, iters %s"
+              % (args.warmup + f, res[-1]["ms_total"], res[-1]["ms_setup"], res[-1]["ms_pcg"],
+                 res[-1]["pcg_iters"].tolist()), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_frame = 1e3 * wall / args.steps
+    dof_iters = sum(float(body.m) * float(r["pcg_iters"].sum()) for r in res)
+    pcg_s = sum(r["ms_pcg"] for r in res) / 1e3
+    value = dof_iters / pcg_s
+    spmv_calls = sum(r["spmv_calls"] for r in res)
+    spmv_ms = sum(r["spmv_ms"] for r in res)
+    roof = None
+    if spmv_calls:
+        avg_ms = spmv_ms / spmv_calls
+        nbytes = spmv_bytes(body.m, body.nnz)
+        ach = nbytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "k_pcg_spmv_dot (fine-level A p with p^T A p)",
+                "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
+                "launches": int(spmv_calls)}
+    out = {
+        "metric": METRIC, "value": value, "unit": "constraint-DOF*iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_frame,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == B.PREC_FP64 else "f32 V-cycle / f64 PCG",
+        "data": "synthetic",
+        "config": {"workload": w.name, "rows": body.m, "nnz": body.nnz,
+                   "iters_per_frame": n_iters, "precision": args.precision,
+                   "reuse_interval": args.reuse, "tol": 1e-6,
+                   "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
+                   "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
+                   "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps},
+        "roofline": roof,
+    }
+    body.close()
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(w)
+        print("cpu baseline took %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,387 @@
+"""Thin ctypes binding of the C ABI in include/mgpbd.h.
+
+Argument marshalling only: every step runs in the HIP library. Device
+arrays are torch cuda tensors (float64 / int32 / int64, contiguous); their
+data pointers are handed to the library together with the current torch
+stream. The library must be built (paper_2505_13390_amd/build.py); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgpbd_hip.so")
+
+OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_NOT_CONVERGED, E_BREAKDOWN, E_SETUP, E_STATE = range(8)
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class Options(C.Structure):
+    _fields_ = [("theta", C.c_double), ("gs_sweeps", C.c_int32), ("pre_sweeps", C.c_int32),
+                ("post_sweeps", C.c_int32), ("lambda_min", C.c_double),
+                ("coarse_max", C.c_int32), ("dense_max", C.c_int32), ("max_levels", C.c_int32),
+                ("power_iters", C.c_int32), ("omega_relax", C.c_double), ("tol", C.c_double),
+                ("max_pcg", C.c_int32), ("seed", C.c_uint64), ("reuse_interval", C.c_int32),
+                ("b_mode", C.c_int32), ("eps_b", C.c_double), ("precision", C.c_int32),
+                ("lmax_scale", C.c_double), ("check_every", C.c_int32),
+                ("use_graph", C.c_int32), ("profile_spmv", C.c_int32)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_verts", C.c_int64), ("rest", C.c_void_p), ("inv_mass", C.c_void_p),
+                ("n_tets", C.c_int64), ("tets", C.c_void_p)]
+
+
+class Constraints(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("edges", C.c_void_p), ("n_vols", C.c_int64),
+                ("vol_tet", C.c_void_p)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("bnorm", C.c_void_p), ("pcg_iters", C.c_void_p), ("pcg_ratio", C.c_void_p),
+                ("setup_ran", C.c_void_p), ("iters_done", C.c_int32), ("ms_setup", C.c_double),
+                ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("spmv_calls", C.c_int64),
+                ("spmv_ms", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ratio", C.c_double), ("ms_setup", C.c_double),
+                ("ms_solve", C.c_double)]
+
+
+class MgpbdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("mgpbd status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "mgpbd_default_options": (None, [C.POINTER(Options)]),
+    "mgpbd_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Constraints), C.c_void_p, C.c_double,
+                               C.c_void_p, C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "mgpbd_solver_create": (C.c_int, [C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "mgpbd_setup": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "mgpbd_step": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.POINTER(StepStats)]),
+    "mgpbd_solve": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_double, C.c_void_p,
+                              C.POINTER(SolveStats)]),
+    "mgpbd_destroy": (None, [C.c_void_p]),
+    "mgpbd_last_error": (C.c_char_p, [C.c_void_p]),
+    "mgpbd_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgpbd_force_pcg_iters": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "mgpbd_num_rows": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "mgpbd_num_levels": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "mgpbd_get_level": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_int64)]),
+    "mgpbd_get_aggregates": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mgpbd_get_transfer": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mgpbd_get_matrix": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mgpbd_get_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgpbd_get_lambda": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgpbd_get_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "mgpbd_selftest_sqrt_div": (C.c_int, [C.c_int64] + [C.c_void_p] * 4),
+    "mgpbd_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mgpbd_batch_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mgpbd_batch_destroy": (None, [C.c_void_p]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load the HIP library; raises if it was not built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run paper_2505_13390_amd/build.py"
+                               % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t, dtype=None):
+    """Device pointer of a contiguous cuda tensor (checks dtype/device)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a cuda tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(ctx, st):
+    if st != OK:
+        msg = lib().mgpbd_last_error(ctx) if ctx else b""
+        raise MgpbdError(st, (msg or b"").decode())
+
+
+def mgpbd_default_options(**overrides) -> Options:
+    o = Options()
+    lib().mgpbd_default_options(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prepare(ctx):
+    """Order the library's work after torch's: use torch's current stream; if
+    that is the legacy default stream (which the library does not capture
+    graphs on), wait for the device first and let the library use its own
+    stream. The library itself returns only after its work has completed."""
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    _check(ctx, lib().mgpbd_set_stream(ctx, C.c_void_p(s) if s else None))
+    if not s:
+        torch.cuda.synchronize()
+
+
+def mgpbd_create(rest, inv_mass, tets, edges, vol_tet, compliance, dt, gravity,
+                 opt: Options | None = None):
+    """Create a body context from host arrays (numpy). Returns the handle."""
+    rest = np.ascontiguousarray(rest, np.float64)
+    inv_mass = np.ascontiguousarray(inv_mass, np.float64)
+    tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
+    edges = np.ascontiguousarray(edges, np.int32).reshape(-1, 2)
+    vol_tet = np.ascontiguousarray(vol_tet, np.int32)
+    comp = np.ascontiguousarray(compliance, np.float64)
+    grav = np.ascontiguousarray(gravity, np.float64)
+    mesh = Mesh(rest.shape[0], _np_ptr(rest).value, _np_ptr(inv_mass).value, tets.shape[0],
+                _np_ptr(tets).value)
+    cons = Constraints(edges.shape[0], _np_ptr(edges).value, vol_tet.shape[0],
+                       _np_ptr(vol_tet).value)
+    h = C.c_void_p()
+    st = lib().mgpbd_create(C.byref(mesh), C.byref(cons), _np_ptr(comp), float(dt),
+                            _np_ptr(grav), C.byref(opt) if opt is not None else None, C.byref(h))
+    if st != OK:
+        raise MgpbdError(st, "mgpbd_create")
+    return h
+
+
+def mgpbd_solver_create(opt: Options | None = None):
+    h = C.c_void_p()
+    st = lib().mgpbd_solver_create(C.byref(opt) if opt is not None else None, C.byref(h))
+    if st != OK:
+        raise MgpbdError(st, "mgpbd_solver_create")
+    return h
+
+
+def mgpbd_setup(ctx, max_levels: int, reuse_interval: int):
+    _check(ctx, lib().mgpbd_setup(ctx, max_levels, reuse_interval))
+
+
+def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
+    import torch
+    f64 = torch.float64
+    n = max(int(n_iters), 1)
+    bn = np.zeros(n)
+    its = np.zeros(n, np.int32)
+    ratio = np.zeros(n)
+    setup = np.zeros(n, np.int32)
+    st = StepStats(_np_ptr(bn).value, _np_ptr(its).value, _np_ptr(ratio).value,
+                   _np_ptr(setup).value, 0, 0.0, 0.0, 0.0, 0, 0.0)
+    _prepare(ctx)
+    s = lib().mgpbd_step(ctx, _dev(x, f64), _dev(y, f64), _dev(z, f64), _dev(vx, f64),
+                         _dev(vy, f64), _dev(vz, f64), int(n_iters),
+                         C.byref(st) if stats else None)
+    _check(ctx, s)
+    k = st.iters_done
+    return dict(bnorm=bn[:k], pcg_iters=its[:k], pcg_ratio=ratio[:k], setup_ran=setup[:k],
+                iters_done=k, ms_setup=st.ms_setup, ms_pcg=st.ms_pcg, ms_total=st.ms_total,
+                spmv_calls=st.spmv_calls, spmv_ms=st.spmv_ms)
+
+
+def mgpbd_solve(ctx, rowptr, col, val, b, tol, x_out):
+    import torch
+    csr = Csr(rowptr.numel() - 1, col.numel(), _dev(rowptr, torch.int64).value,
+              _dev(col, torch.int32).value, _dev(val, torch.float64).value)
+    st = SolveStats()
+    _prepare(ctx)
+    s = lib().mgpbd_solve(ctx, C.byref(csr), _dev(b, torch.float64), float(tol),
+                          _dev(x_out, torch.float64), C.byref(st))
+    if s not in (OK, E_NOT_CONVERGED):
+        _check(ctx, s)
+    return dict(status=s, iters=st.iters, ratio=st.ratio, ms_setup=st.ms_setup,
+                ms_solve=st.ms_solve)
+
+
+def mgpbd_destroy(ctx):
+    if ctx:
+        lib().mgpbd_destroy(ctx)
+
+
+def mgpbd_set_stream(ctx, stream_ptr: int):
+    _check(ctx, lib().mgpbd_set_stream(ctx, C.c_void_p(stream_ptr)))
+
+
+def mgpbd_force_pcg_iters(ctx, iters):
+    if iters is None:
+        _check(ctx, lib().mgpbd_force_pcg_iters(ctx, None, 0))
+        return
+    a = np.ascontiguousarray(iters, np.int32)
+    _check(ctx, lib().mgpbd_force_pcg_iters(ctx, _np_ptr(a), a.shape[0]))
+
+
+def mgpbd_num_rows(ctx):
+    m, nnz = C.c_int64(), C.c_int64()
+    _check(ctx, lib().mgpbd_num_rows(ctx, C.byref(m), C.byref(nnz)))
+    return m.value, nnz.value
+
+
+def mgpbd_num_levels(ctx):
+    l = C.c_int32()
+    _check(ctx, lib().mgpbd_num_levels(ctx, C.byref(l)))
+    return l.value
+
+
+def mgpbd_get_level(ctx, l):
+    n, nnz, na = C.c_int64(), C.c_int64(), C.c_int64()
+    om = C.c_double()
+    _check(ctx, lib().mgpbd_get_level(ctx, l, C.byref(n), C.byref(nnz), C.byref(om),
+                                      C.byref(na)))
+    return dict(n=n.value, nnz=nnz.value, omega=om.value, n_agg=na.value)
+
+
+def mgpbd_get_aggregates(ctx, l):
+    n = mgpbd_get_level(ctx, l)["n"]
+    out = np.zeros(n, np.int32)
+    _check(ctx, lib().mgpbd_get_aggregates(ctx, l, _np_ptr(out)))
+    return out
+
+
+def mgpbd_get_transfer(ctx, l):
+    n = mgpbd_get_level(ctx, l)["n"]
+    p = np.zeros(n)
+    B = np.zeros(n)
+    _check(ctx, lib().mgpbd_get_transfer(ctx, l, _np_ptr(p), _np_ptr(B)))
+    return p, B
+
+
+def mgpbd_get_matrix(ctx, l):
+    info = mgpbd_get_level(ctx, l)
+    rp = np.zeros(info["n"] + 1, np.int64)
+    col = np.zeros(info["nnz"], np.int32)
+    val = np.zeros(info["nnz"])
+    _check(ctx, lib().mgpbd_get_matrix(ctx, l, _np_ptr(rp), _np_ptr(col), _np_ptr(val)))
+    return rp, col, val
+
+
+def mgpbd_get_rhs(ctx, m):
+    out = np.zeros(m)
+    _check(ctx, lib().mgpbd_get_rhs(ctx, _np_ptr(out)))
+    return out
+
+
+def mgpbd_get_lambda(ctx, m):
+    out = np.zeros(m)
+    _check(ctx, lib().mgpbd_get_lambda(ctx, _np_ptr(out)))
+    return out
+
+
+def mgpbd_get_colors(ctx, m):
+    out = np.zeros(m, np.int32)
+    nc = C.c_int32()
+    _check(ctx, lib().mgpbd_get_colors(ctx, _np_ptr(out), C.byref(nc)))
+    return out, nc.value
+
+
+def mgpbd_selftest_sqrt_div(a, b):
+    import torch
+    s = torch.empty_like(a)
+    q = torch.empty_like(a)
+    torch.cuda.synchronize()
+    st = lib().mgpbd_selftest_sqrt_div(a.numel(), _dev(a, torch.float64), _dev(b, torch.float64),
+                                       _dev(s, torch.float64), _dev(q, torch.float64))
+    if st != OK:
+        raise MgpbdError(st, "selftest")
+    return s, q
+
+
+def mgpbd_batch_create(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    h = C.c_void_p()
+    st = lib().mgpbd_batch_create(arr, len(ctxs), C.byref(h))
+    if st != OK:
+        raise MgpbdError(st, "mgpbd_batch_create")
+    return h
+
+
+def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters):
+    import torch
+    xs = (C.c_void_p * (3 * len(xyz_list)))()
+    vs = (C.c_void_p * (3 * len(vxyz_list)))()
+    for k, (p, v) in enumerate(zip(xyz_list, vxyz_list)):
+        for d in range(3):
+            xs[3 * k + d] = _dev(p[d], torch.float64).value
+            vs[3 * k + d] = _dev(v[d], torch.float64).value
+    torch.cuda.synchronize()
+    st = lib().mgpbd_batch_step(batch, xs, vs, int(n_iters), None)
+    if st != OK:
+        raise MgpbdError(st, "mgpbd_batch_step")
+
+
+def mgpbd_batch_destroy(batch):
+    if batch:
+        lib().mgpbd_batch_destroy(batch)
+
+
+class Body:
+    """Convenience owner of one body context and its device state."""
+
+    def __init__(self, w, opt: Options | None = None, device="cuda:0"):
+        import torch
+        self.w = w
+        self.ctx = mgpbd_create(w.rest, w.inv_mass, w.tets, w.edges, w.vol_tet, w.alpha, w.dt,
+                                w.gravity, opt)
+        self.m, self.nnz = mgpbd_num_rows(self.ctx)
+        t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+        self.x = [t(w.x0[:, k]) for k in range(3)]
+        self.v = [t(w.v0[:, k]) for k in range(3)]
+
+    def step(self, n_iters, stats=True):
+        return mgpbd_step(self.ctx, *self.x, *self.v, n_iters, stats)
+
+    def positions(self):
+        return np.stack([a.cpu().numpy() for a in self.x], axis=1)
+
+    def velocities(self):
+        return np.stack([a.cpu().numpy() for a in self.v], axis=1)
+
+    def close(self):
+        if self.ctx:
+            mgpbd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,165 @@
+// Coarsest level: dense FP64 Cholesky factorisation and explicit inverse.
+// The last level has at most dense_max rows; it is factorised once per global
+// iteration (its Galerkin values change) and every V-cycle then applies the
+// inverse as a dense product. The trailing updates of the factorisation and
+// the product Y^T Y that forms the inverse run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64) in 16 x 16 tiles.
+#include "setup.hpp"
+
+namespace mgpbd {
+
+__global__ void k_zero_dense(int64_t nn, double *D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) D[i] = 0.0;
+}
+__global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rp,
+                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                               double *__restrict__ D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) D[i * n + col[e]] = val[e];
+}
+void launch_csr_to_dense(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                         double *D, hipStream_t s) {
+  if (!n) return;
+  k_zero_dense<<<blocks_for(n * n, kBlock), kBlock, 0, s>>>(n * n, D);
+  k_csr_to_dense<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, rp, col, val, D);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C(16x16 tile at r0, c0) -= A(r0.., k0..k0+kk) * B(c0.., k0..k0+kk)^T with
+// A and B row-major n x n; one wavefront, kk a multiple of 4.
+// MFMA f64 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; lane l holds D[4 (l / 16) + q][l % 16], q = 0..3.
+__device__ __forceinline__ v4d mfma_tile_nt(const double *__restrict__ M, int64_t n, int64_t r0,
+                                            int64_t c0, int64_t k0, int64_t kk, v4d acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ar = r0 + (lane & 15), bc = c0 + (lane & 15);
+  const int kq = lane >> 4;
+  for (int64_t k = k0; k < k0 + kk; k += 4) {
+    double a = M[ar * n + k + kq];
+    double b = M[bc * n + k + kq];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// One workgroup of 256 threads (4 waves). n is padded by the caller to a
+// multiple of 16 with an identity block (the padding does not change the
+// inverse of the leading n x n part).
+__global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, double *__restrict__ D,
+                                                      double *__restrict__ Y,
+                                                      double *__restrict__ Ainv, int *status) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, nw = nthr >> 6, lane = tid & 63;
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // ---- blocked right-looking Cholesky, 16-column panels ----
+  for (int64_t j0 = 0; j0 < np; j0 += 16) {
+    // panel factorisation (columns j0..j0+15), scalar
+    for (int64_t j = j0; j < j0 + 16; ++j) {
+      __syncthreads();
+      if (tid == 0) {
+        double d = D[j * np + j];
+        if (!(d > 0.0)) bad = 1;
+        D[j * np + j] = sqrt(d > 0.0 ? d : 1.0);
+      }
+      __syncthreads();
+      if (bad) break;
+      double ljj = D[j * np + j];
+      for (int64_t i = j + 1 + tid; i < np; i += nthr) D[i * np + j] = D[i * np + j] / ljj;
+      __syncthreads();
+      // update the rest of the panel columns j+1..j0+15 for all rows below
+      for (int64_t idx = tid; idx < (np - j - 1) * (j0 + 15 - j); idx += nthr) {
+        int64_t w = j0 + 15 - j;
+        int64_t i = j + 1 + idx / w, k = j + 1 + idx % w;
+        if (k <= i) D[i * np + k] = D[i * np + k] - D[i * np + j] * D[k * np + j];
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    // trailing update with the FP64 matrix cores: tiles (ti, tk) below the
+    // panel, tk <= ti, D[ti,tk] -= L[ti, panel] L[tk, panel]^T
+    int64_t t0 = j0 + 16;
+    int64_t nt = (np - t0) / 16;
+    for (int64_t t = wave; t < nt * (nt + 1) / 2; t += nw) {
+      // map t -> (ti, tk) with tk <= ti
+      int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      while (ti * (ti + 1) / 2 > t) --ti;
+      int64_t tk = t - ti * (ti + 1) / 2;
+      int64_t r0 = t0 + ti * 16, c0 = t0 + tk * 16;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mfma_tile_nt(D, np, r0, c0, j0, 16, acc);
+      const int cc = lane & 15, rb = (lane >> 4) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int64_t rr = r0 + rb + q, cl = c0 + cc;
+        if (cl <= rr) D[rr * np + cl] = D[rr * np + cl] - acc[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) *status = 1;
+    return;
+  }
+  // ---- Y = L^-1 (lower): column c solved by one thread ----
+  for (int64_t c = tid; c < np; c += nthr) {
+    for (int64_t i = 0; i < c; ++i) Y[i * np + c] = 0.0;
+    for (int64_t i = c; i < np; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int64_t k = c; k < i; ++k) s -= D[i * np + k] * Y[k * np + c];
+      Y[i * np + c] = s / D[i * np + i];
+    }
+  }
+  __syncthreads();
+  // ---- Ainv = Y^T Y on the matrix cores: Ainv[r][c] = sum_k Y[k][r] Y[k][c].
+  // Transpose Y into D (the factor is no longer needed) so both operands are
+  // read along rows: Ainv = Z Z^T with Z = Y^T.
+  for (int64_t idx = tid; idx < np * np; idx += nthr) {
+    int64_t i = idx / np, k = idx % np;
+    D[k * np + i] = Y[i * np + k];
+  }
+  __syncthreads();
+  int64_t nt = np / 16;
+  for (int64_t t = wave; t < nt * nt; t += nw) {
+    int64_t ti = t / nt, tk = t % nt;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    int64_t kstart = (ti > tk ? ti : tk) * 16;   // Z[r][k] = Y[k][r] = 0 for k < r
+    acc = mfma_tile_nt(D, np, ti * 16, tk * 16, kstart, np - kstart, acc);
+    const int cc = lane & 15, rb = (lane >> 4) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int64_t rr = ti * 16 + rb + q, cl = tk * 16 + cc;
+      if (rr < n && cl < n) Ainv[rr * n + cl] = acc[q];
+    }
+  }
+  if (tid == 0) *status = 0;
+}
+
+__global__ void k_pad_dense(int64_t n, int64_t np, const double *__restrict__ D,
+                            double *__restrict__ P) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= np * np) return;
+  int64_t i = idx / np, k = idx % np;
+  double v;
+  if (i < n && k < n) v = D[i * n + k];
+  else v = (i == k) ? 1.0 : 0.0;
+  P[idx] = v;
+}
+
+// D: n x n input (destroyed); Y: scratch of np x np; the padded factor is
+// formed in Y's companion region, so Y must hold 2 np^2 doubles.
+void launch_chol_inverse(int64_t n, double *D, double *Y, double *Ainv, int *status,
+                         hipStream_t s) {
+  if (!n) return;
+  int64_t np = (n + 15) / 16 * 16;
+  double *Pd = Y + np * np;   // padded copy of D
+  k_pad_dense<<<blocks_for(np * np, kBlock), kBlock, 0, s>>>(n, np, D, Pd);
+  k_chol_inverse<<<1, 256, 0, s>>>(n, np, Pd, Y, Ainv, status);
+}
+
+}  // namespace mgpbd

@@ -1,0 +1,650 @@
+// Sparse kernels of the solving phase (Sec. 4.4-4.5): CSR products with G
+// lanes per row and fixed-tree group sums, the omega-Jacobi smoother, the
+// residual, restriction / prolongation through the aggregate lists, the
+// dense coarsest solve, and the FP64 PCG loop with deterministic grid
+// reductions and a device-resident control block (no host round trip per
+// iteration; every kernel returns at once when the solve is finished).
+#include "kernels.hpp"
+
+namespace mgpbd {
+
+int lanes_for_rowlen(double mean) {
+  if (mean >= 96.0) return 32;
+  if (mean >= 24.0) return 16;
+  if (mean >= 10.0) return 8;
+  return 4;
+}
+
+#define MG_DISPATCH_G(lanes, LAUNCH) \
+  switch (lanes) {                   \
+    case 4: LAUNCH(4); break;        \
+    case 8: LAUNCH(8); break;        \
+    case 16: LAUNCH(16); break;      \
+    case 32: LAUNCH(32); break;      \
+    default: LAUNCH(64); break;      \
+  }
+
+// sum over the row [lo, hi) of val[e] * x[col[e]], G lanes, fixed tree
+template <int G, class T>
+__device__ __forceinline__ T row_dot(int64_t lo, int64_t hi, int sub, const int32_t *__restrict__ col,
+                                     const T *__restrict__ val, const T *__restrict__ x) {
+  T s = 0;
+#pragma unroll 4
+  for (int64_t e = lo + sub; e < hi; e += G) s += val[e] * x[col[e]];
+  return group_sum<G>(s);
+}
+
+// ------------------------------------------------------------------ SpMV
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const int64_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col,
+                                                 const T *__restrict__ val,
+                                                 const T *__restrict__ x, T *__restrict__ y) {
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t i = base + grp;
+    bool ok = i < hi;
+    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, x);
+    if (ok && sub == 0) y[i] = s;
+  }
+}
+
+template <class T>
+void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s) {
+  if (A.n == 0) return;
+  int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) k_spmv<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+
+// ------------------------------------------------------------ smoother
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_first(int64_t n, const T *__restrict__ dinv,
+                                                         const T *__restrict__ r, T omega,
+                                                         T *__restrict__ z, const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) z[i] = omega * (r[i] * dinv[i]);
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_first2(int64_t n, const int64_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col,
+                                                          const T *__restrict__ val,
+                                                          const T *__restrict__ dinv,
+                                                          const T *__restrict__ r, T omega,
+                                                          T *__restrict__ z, const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t i = base + grp;
+    bool ok = i < hi;
+    int64_t a = ok ? rp[i] : 0, b = ok ? rp[i + 1] : 0;
+    T s = 0;
+#pragma unroll 4
+    for (int64_t e = a + sub; e < b; e += G) {
+      int32_t j = col[e];
+      s += val[e] * (omega * (r[j] * dinv[j]));
+    }
+    s = group_sum<G>(s);
+    if (ok && sub == 0) {
+      T ri = r[i], di = dinv[i];
+      T z1 = omega * (ri * di);
+      z[i] = z1 + omega * ((ri - s) * di);
+    }
+  }
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const T *__restrict__ dinv,
+                                                   const T *__restrict__ r, T omega,
+                                                   const T *__restrict__ zi, T *__restrict__ zo,
+                                                   const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t i = base + grp;
+    bool ok = i < hi;
+    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, zi);
+    if (ok && sub == 0) zo[i] = zi[i] + omega * ((r[i] - s) * dinv[i]);
+  }
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const T *__restrict__ val,
+                                                     const T *__restrict__ r,
+                                                     const T *__restrict__ z,
+                                                     T *__restrict__ res, const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t i = base + grp;
+    bool ok = i < hi;
+    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, z);
+    if (ok && sub == 0) res[i] = r[i] - s;
+  }
+}
+
+template <class T>
+void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z, const int *done,
+                         hipStream_t s) {
+  if (n == 0) return;
+  k_jacobi_first<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dinv, r, omega, z, done);
+}
+template <class T>
+void launch_jacobi_first2(const CsrView<T> &A, const T *dinv, const T *r, T omega, T *z,
+                          const int *done, hipStream_t s) {
+  if (A.n == 0) return;
+  int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) \
+  k_jacobi_first2<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, dinv, r, omega, z, done)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+template <class T>
+void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega, const T *zi, T *zo,
+                   const int *done, hipStream_t s) {
+  if (A.n == 0) return;
+  int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) \
+  k_jacobi<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, dinv, r, omega, zi, zo, done)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+template <class T>
+void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
+                     hipStream_t s) {
+  if (A.n == 0) return;
+  int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) k_residual<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, r, z, res, done)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+
+// ------------------------------------------------------------ transfers
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_restrict(int64_t na, const int64_t *__restrict__ ap,
+                                                     const int32_t *__restrict__ mem,
+                                                     const T *__restrict__ p,
+                                                     const T *__restrict__ res,
+                                                     T *__restrict__ rc, const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(na, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t a = base + grp;
+    bool ok = a < hi;
+    int64_t b0 = ok ? ap[a] : 0, b1 = ok ? ap[a + 1] : 0;
+    T s = 0;
+    for (int64_t k = b0 + sub; k < b1; k += G) {
+      int32_t i = mem[k];
+      s += p[i] * res[i];
+    }
+    s = group_sum<G>(s);
+    if (ok && sub == 0) rc[a] = s;
+  }
+}
+
+template <class T>
+void launch_restrict(int64_t na, const int64_t *ap, const int32_t *mem, const T *p, const T *res,
+                     T *rc, const int *done, hipStream_t s) {
+  if (na == 0) return;
+  int grid = grid_for(na * 8, kBlock);
+  k_restrict<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t *__restrict__ agg,
+                                                    const T *__restrict__ p,
+                                                    const T *__restrict__ ec,
+                                                    T *__restrict__ z, const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    int32_t a = agg[i];
+    if (a >= 0) z[i] = z[i] + p[i] * ec[a];
+  }
+}
+
+template <class T>
+void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec, T *z, const int *done,
+                    hipStream_t s) {
+  if (n == 0) return;
+  k_prolong<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, agg, p, ec, z, done);
+}
+
+// one wavefront per row of the dense inverse
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dense_apply(int64_t n, const double *__restrict__ Ainv,
+                                                        const T *__restrict__ rc,
+                                                        T *__restrict__ ec, const int *done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x % kWave;
+  int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  bool ok = row < n;
+  double s = 0.0;
+  if (ok)
+    for (int64_t k = lane; k < n; k += kWave) s += Ainv[row * n + k] * (double)rc[k];
+  s = group_sum<kWave>(s);
+  if (ok && lane == 0) ec[row] = (T)s;
+}
+
+template <class T>
+void launch_dense_apply(int64_t n, const double *Ainv, const T *rc, T *ec, const int *done,
+                        hipStream_t s) {
+  if (n == 0) return;
+  k_dense_apply<T><<<blocks_for(n, kBlock / kWave), kBlock, 0, s>>>(n, Ainv, rc, ec, done);
+}
+
+// ------------------------------------------------------------ utilities
+__global__ void k_d2f(int64_t n, const double *__restrict__ in, float *__restrict__ out,
+                      const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = (float)in[i];
+}
+void launch_d2f(int64_t n, const double *in, float *out, const int *done, hipStream_t s) {
+  if (n) k_d2f<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
+}
+__global__ void k_f2d(int64_t n, const float *__restrict__ in, double *__restrict__ out,
+                      const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = (double)in[i];
+}
+void launch_f2d(int64_t n, const float *in, double *out, const int *done, hipStream_t s) {
+  if (n) k_f2d<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
+}
+template <class T>
+__global__ void k_copy_t(int64_t n, const T *__restrict__ in, T *__restrict__ out, const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = in[i];
+}
+template <class T>
+void launch_copy_t(int64_t n, const T *in, T *out, const int *done, hipStream_t s) {
+  if (n) k_copy_t<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
+}
+template <class T>
+__global__ void k_zero_t(int64_t n, T *__restrict__ out, const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = (T)0;
+}
+template <class T>
+void launch_zero_t(int64_t n, T *out, const int *done, hipStream_t s) {
+  if (n) k_zero_t<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, out, done);
+}
+__global__ void k_copy(int64_t n, const double *__restrict__ in, double *__restrict__ out,
+                       const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = in[i];
+}
+void launch_copy(int64_t n, const double *in, double *out, const int *done, hipStream_t s) {
+  if (n) k_copy<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
+}
+template <class V>
+__global__ void k_fill(int64_t n, V v, V *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = v;
+}
+void launch_fill(int64_t n, double v, double *out, hipStream_t s) {
+  if (n) k_fill<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, v, out);
+}
+void launch_fill_i32(int64_t n, int32_t v, int32_t *out, hipStream_t s) {
+  if (n) k_fill<int32_t><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, v, out);
+}
+void launch_fill_u8(int64_t n, uint8_t v, uint8_t *out, hipStream_t s) {
+  if (n) k_fill<uint8_t><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, v, out);
+}
+
+// ------------------------------------------------------------------ PCG
+__global__ __launch_bounds__(kBlock) void k_pcg_init(PcgCtl *ctl, int64_t n,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ x,
+                                                     double *__restrict__ r, RedBuf rb) {
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[1] = {0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double bi = b[i];
+    x[i] = 0.0;
+    r[i] = bi;
+    v[0] += bi * bi;
+  }
+  double tot[1];
+  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+    ctl->bnorm = sqrt(tot[0]);
+    ctl->iters = 0;
+    ctl->ratio = 0.0;
+    ctl->rr = tot[0];
+    ctl->done = (ctl->bnorm == 0.0) ? 1 : 0;
+    if (!(tot[0] == tot[0]) || tot[0] > 1.7976931348623157e308) ctl->done = 2;
+  }
+}
+void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double *r, RedBuf rb,
+                     hipStream_t s) {
+  k_pcg_init<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, b, x, r, rb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_init_p(PcgCtl *ctl, int64_t n,
+                                                       const double *__restrict__ r,
+                                                       const double *__restrict__ z,
+                                                       double *__restrict__ p,
+                                                       double *__restrict__ zold, int flexible,
+                                                       RedBuf rb) {
+  if (ctl->done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[1] = {0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double zi = z[i];
+    p[i] = zi;
+    if (flexible) zold[i] = zi;
+    v[0] += r[i] * zi;
+  }
+  double tot[1];
+  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+    ctl->rho = tot[0];
+    if (!(tot[0] > 0.0)) ctl->done = 2;
+  }
+}
+void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
+                       double *zold, bool flexible, RedBuf rb, hipStream_t s) {
+  k_pcg_init_p<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, r, z, p, zold, flexible ? 1 : 0, rb);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv_dot(PcgCtl *ctl, int64_t n,
+                                                         const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ p,
+                                                         double *__restrict__ q, RedBuf rb) {
+  if (ctl->done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[1] = {0.0};
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t i = base + grp;
+    bool ok = i < hi;
+    double s = row_dot<G, double>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, p);
+    if (ok && sub == 0) {
+      q[i] = s;
+      v[0] += p[i] * s;
+    }
+  }
+  double tot[1];
+  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+    ctl->pq = tot[0];
+    if (!(tot[0] > 0.0) || !(ctl->rho > 0.0)) {
+      ctl->done = 2;
+    } else {
+      ctl->alpha = ctl->rho / tot[0];
+    }
+  }
+}
+void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
+                         RedBuf rb, hipStream_t s) {
+  int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) k_pcg_spmv_dot<G><<<grid, kBlock, 0, s>>>(ctl, A.n, A.rowptr, A.col, A.val, p, q, rb)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_update(PcgCtl *ctl, int64_t n,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ q,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ r, RedBuf rb) {
+  if (ctl->done) return;
+  const double alpha = ctl->alpha;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[1] = {0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    x[i] = x[i] + alpha * p[i];
+    double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  double tot[1];
+  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+    int it = ctl->iters + 1;
+    ctl->iters = it;
+    ctl->rr = tot[0];
+    double ratio = sqrt(tot[0]) / ctl->bnorm;
+    ctl->ratio = ratio;
+    if (!(ratio == ratio)) ctl->done = 2;
+    else if (ctl->force > 0) { if (it >= ctl->force) ctl->done = 3; }
+    else if (ratio <= ctl->tol) ctl->done = 1;
+    else if (it >= ctl->max_iters) ctl->done = 4;
+  }
+}
+void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,
+                       double *r, RedBuf rb, hipStream_t s) {
+  k_pcg_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, p, q, x, r, rb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_rz(PcgCtl *ctl, int64_t n,
+                                                   const double *__restrict__ r,
+                                                   double *__restrict__ z,
+                                                   const float *__restrict__ z32,
+                                                   double *__restrict__ zold, int flexible,
+                                                   RedBuf rb) {
+  if (ctl->done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double zi;
+    if (z32) {
+      zi = (double)z32[i];
+      z[i] = zi;
+    } else {
+      zi = z[i];
+    }
+    double ri = r[i];
+    v[0] += ri * zi;
+    if (flexible) {
+      v[1] += ri * (zi - zold[i]);
+      zold[i] = zi;
+    }
+  }
+  double tot[2];
+  if (grid_reduce<2>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+    double rho_new = tot[0];
+    double num = flexible ? tot[1] : rho_new;
+    ctl->beta = num / ctl->rho;
+    ctl->rho = rho_new;
+    if (!(rho_new > 0.0)) ctl->done = 2;
+  }
+}
+void launch_pcg_rz(PcgCtl *ctl, int64_t n, const double *r, double *z, const float *z32,
+                   double *zold, bool flexible, RedBuf rb, hipStream_t s) {
+  k_pcg_rz<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, r, z, z32, zold, flexible ? 1 : 0, rb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(PcgCtl *ctl, int64_t n,
+                                                        const double *__restrict__ z,
+                                                        double *__restrict__ p) {
+  if (ctl->done) return;
+  const double beta = ctl->beta;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) p[i] = z[i] + beta * p[i];
+}
+void launch_pcg_pupdate(PcgCtl *ctl, int64_t n, const double *z, double *p, hipStream_t s) {
+  k_pcg_pupdate<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, z, p);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
+                                                const double *__restrict__ b, double *out,
+                                                RedBuf rb) {
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  double v[1] = {0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v[0] += a[i] * b[i];
+  double tot[1];
+  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) *out = tot[0];
+}
+void launch_dot(int64_t n, const double *a, const double *b, double *out, RedBuf rb,
+                hipStream_t s) {
+  k_dot<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, a, b, out, rb);
+}
+
+// ------------------------------------------------------------------ scan
+// Three-phase exclusive scan: block sums of 1024-element tiles, a scan of
+// the tile sums (recursive), then the tile-local scan plus tile offset.
+constexpr int kScanTile = 1024;
+
+template <class In>
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const In *in, int64_t n, int64_t *sums) {
+  __shared__ int64_t sh[kBlock / kWave];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+  for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+    int64_t i = base + k;
+    if (i < n) s += (int64_t)in[i];
+  }
+  s = group_sum<kWave>(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+template <class In>
+__global__ __launch_bounds__(kBlock) void k_tile_scan(const In *in, int64_t n, const int64_t *offs,
+                                                      int64_t *out) {
+  // each thread owns 4 consecutive elements of the tile
+  __shared__ int64_t sh[kBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 4;
+  int64_t v[4];
+  int64_t loc = 0;
+  for (int k = 0; k < 4; ++k) {
+    int64_t i = base + k;
+    v[k] = (i < n) ? (int64_t)in[i] : 0;
+    loc += v[k];
+  }
+  sh[threadIdx.x] = loc;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 256 thread sums
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int64_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = offs[blockIdx.x] + sh[threadIdx.x] - loc;
+  for (int k = 0; k < 4; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (blockIdx.x == ntiles - 1 && threadIdx.x == kBlock - 1) out[n] = run;
+}
+
+template <class In>
+static void scan_impl(const In *in, int64_t *out, int64_t n, DevBuf<int64_t> &tmp, size_t tmp_off,
+                      hipStream_t s) {
+  if (n == 0) {
+    MG_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+    return;
+  }
+  int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  // tmp layout from tmp_off: tile sums [ntiles], their exclusive scan [ntiles + 1]
+  size_t need = tmp_off + 2 * (size_t)ntiles + 1;
+  if (tmp.n < need) throw Error(MGPBD_E_SETUP, "scan scratch too small");
+  int64_t *sums = tmp.p + tmp_off;
+  int64_t *offs = sums + ntiles;
+  k_tile_sums<In><<<(unsigned)ntiles, kBlock, 0, s>>>(in, n, sums);
+  if (ntiles == 1) {
+    MG_HIP(hipMemsetAsync(offs, 0, sizeof(int64_t), s));
+  } else {
+    scan_impl<int64_t>(sums, offs, ntiles, tmp, tmp_off + 2 * (size_t)ntiles + 1, s);
+  }
+  k_tile_scan<In><<<(unsigned)ntiles, kBlock, 0, s>>>(in, n, offs, out);
+}
+
+static size_t scan_scratch(int64_t n) {
+  size_t tot = 0;
+  while (true) {
+    int64_t nt = (n + kScanTile - 1) / kScanTile;
+    tot += 2 * (size_t)nt + 1;
+    if (nt <= 1) break;
+    n = nt;
+  }
+  return tot + 8;
+}
+
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, DevBuf<int64_t> &tmp,
+                        hipStream_t s) {
+  tmp.reserve(scan_scratch(n));
+  scan_impl<int64_t>(in, out, n, tmp, 0, s);
+}
+void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBuf<int64_t> &tmp,
+                               hipStream_t s) {
+  tmp.reserve(scan_scratch(n));
+  scan_impl<int32_t>(in, out, n, tmp, 0, s);
+}
+
+// explicit instantiations
+#define MG_INST(T)                                                                                  \
+  template void launch_spmv<T>(const CsrView<T> &, const T *, T *, hipStream_t);                    \
+  template void launch_jacobi_first<T>(int64_t, const T *, const T *, T, T *, const int *,          \
+                                       hipStream_t);                                                \
+  template void launch_jacobi_first2<T>(const CsrView<T> &, const T *, const T *, T, T *,           \
+                                        const int *, hipStream_t);                                  \
+  template void launch_jacobi<T>(const CsrView<T> &, const T *, const T *, T, const T *, T *,       \
+                                 const int *, hipStream_t);                                         \
+  template void launch_residual<T>(const CsrView<T> &, const T *, const T *, T *, const int *,      \
+                                   hipStream_t);                                                    \
+  template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
+                                   T *, const int *, hipStream_t);                                  \
+  template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \
+                                  hipStream_t);                                                     \
+  template void launch_dense_apply<T>(int64_t, const double *, const T *, T *, const int *,         \
+                                      hipStream_t);                                                 \
+  template void launch_copy_t<T>(int64_t, const T *, T *, const int *, hipStream_t);                \
+  template void launch_zero_t<T>(int64_t, T *, const int *, hipStream_t);
+MG_INST(double)
+MG_INST(float)
+#undef MG_INST
+
+}  // namespace mgpbd

@@ -1,0 +1,87 @@
+// Host-callable launchers of the library's HIP kernels. Every launcher
+// enqueues on the given stream and returns immediately.
+#pragma once
+
+#include "common.hpp"
+#include "devutil.hpp"
+
+namespace mgpbd {
+
+// Lanes per row used by the row-group CSR kernels for a given mean row length.
+int lanes_for_rowlen(double mean_nnz_per_row);
+
+// CSR view of one level (device pointers).
+template <class T>
+struct CsrView {
+  int64_t n = 0, nnz = 0;
+  const int64_t *rowptr = nullptr;
+  const int32_t *col = nullptr;
+  const T *val = nullptr;
+  int lanes = 16;
+};
+
+// ---------------- sparse kernels of the V-cycle (T = double or float) ----
+template <class T> void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s);
+// z = omega D^-1 r (first sweep from z = 0)
+template <class T> void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z,
+                                            const int *done, hipStream_t s);
+// z = z1 + omega D^-1 (r - A z1) with z1 = omega D^-1 r formed on the fly
+template <class T> void launch_jacobi_first2(const CsrView<T> &A, const T *dinv, const T *r,
+                                             T omega, T *z, const int *done, hipStream_t s);
+// zo = zi + omega D^-1 (r - A zi)
+template <class T> void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega,
+                                      const T *zi, T *zo, const int *done, hipStream_t s);
+// res = r - A z
+template <class T> void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res,
+                                        const int *done, hipStream_t s);
+// rc[a] = sum over members i of a (ascending) of p_i res_i
+template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
+                                        const int32_t *agg_mem, const T *p, const T *res, T *rc,
+                                        const int *done, hipStream_t s);
+// z_i += p_i ec[agg_i]
+template <class T> void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec,
+                                       T *z, const int *done, hipStream_t s);
+// ec = Ainv rc (FP64 dense, n <= dense_max)
+template <class T> void launch_dense_apply(int64_t n, const double *Ainv, const T *rc, T *ec,
+                                           const int *done, hipStream_t s);
+
+void launch_d2f(int64_t n, const double *in, float *out, const int *done, hipStream_t s);
+void launch_f2d(int64_t n, const float *in, double *out, const int *done, hipStream_t s);
+template <class T> void launch_copy_t(int64_t n, const T *in, T *out, const int *done, hipStream_t s);
+template <class T> void launch_zero_t(int64_t n, T *out, const int *done, hipStream_t s);
+void launch_copy(int64_t n, const double *in, double *out, const int *done, hipStream_t s);
+void launch_fill(int64_t n, double v, double *out, hipStream_t s);
+void launch_fill_i32(int64_t n, int32_t v, int32_t *out, hipStream_t s);
+void launch_fill_u8(int64_t n, uint8_t v, uint8_t *out, hipStream_t s);
+
+// ---------------- PCG (FP64 outer loop), control block in device memory ----
+struct RedBuf {  // partial sums + ticket for grid_reduce (up to 2 values)
+  double *partials = nullptr;
+  unsigned *ticket = nullptr;
+};
+void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double *r, RedBuf rb,
+                     hipStream_t s);
+void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
+                       double *zold, bool flexible, RedBuf rb, hipStream_t s);
+void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
+                         RedBuf rb, hipStream_t s);
+void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,
+                       double *r, RedBuf rb, hipStream_t s);
+// rho_new = r^T z (flexible: beta numerator r^T (z - zold), zold <- z); z32 != nullptr:
+// z = (double) z32 first (mixed precision V-cycle output)
+void launch_pcg_rz(PcgCtl *ctl, int64_t n, const double *r, double *z, const float *z32,
+                   double *zold, bool flexible, RedBuf rb, hipStream_t s);
+void launch_pcg_pupdate(PcgCtl *ctl, int64_t n, const double *z, double *p, hipStream_t s);
+
+// generic deterministic reductions into a device scalar
+void launch_dot(int64_t n, const double *a, const double *b, double *out, RedBuf rb,
+                hipStream_t s);
+
+// ---------------- scans (deterministic) ----------------
+// out[i] = sum_{k<i} in[k], out[n] = total (out has n+1 entries)
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, DevBuf<int64_t> &tmp,
+                        hipStream_t s);
+void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n,
+                               DevBuf<int64_t> &tmp, hipStream_t s);
+
+}  // namespace mgpbd

@@ -1,0 +1,526 @@
+// AMG setup and MGPCG orchestration (host side). See solver.hpp.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+
+namespace mgpbd {
+
+template <class V>
+static V read_dev(const V *d, hipStream_t st, void *pinned) {
+  V *h = static_cast<V *>(pinned);
+  MG_HIP(hipMemcpyAsync(h, d, sizeof(V), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  return *h;
+}
+
+enum Flag { kFBadDiag = 0, kFOverflow, kFUndecided, kFRemaining, kFColorOver, kFChol, kFMirror,
+            kFDiagMissing, kNumFlags };
+
+Solver::Solver(const mgpbd_options &o) : opt(o) {
+  lev.emplace_back(new Level());
+  nlev = 1;
+  ctl.alloc(1);
+  red_partials.alloc(2 * (size_t)kMaxGrid);
+  red_ticket.alloc(1);
+  MG_HIP(hipMemset(red_ticket.p, 0, sizeof(unsigned)));
+  dscal.alloc(16);
+  flags.alloc(kNumFlags);
+  amax.alloc(1);
+  MG_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
+}
+
+Solver::~Solver() {
+  invalidate_graph();
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+void Solver::set_stream(hipStream_t s) {
+  if (s != st) invalidate_graph();
+  st = s;
+}
+
+void Solver::invalidate_graph() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  gexec = nullptr;
+  graph = nullptr;
+  graph_ok = false;
+}
+
+const int *Solver::done_ptr() const {
+  return reinterpret_cast<const int *>(reinterpret_cast<const char *>(ctl.p) +
+                                       offsetof(PcgCtl, done));
+}
+
+void Solver::reset_flags() { MG_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * kNumFlags, st)); }
+
+int Solver::read_flag(int k) {
+  int *h = static_cast<int *>(pinned);
+  MG_HIP(hipMemcpyAsync(h, flags.p + k, sizeof(int), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  return *h;
+}
+
+
+double Solver::norm2(const double *v, int64_t n) {
+  launch_dot(n, v, v, dscal.p + 8, rb(), st);
+  return read_dev(dscal.p + 8, st, pinned);
+}
+
+// ------------------------------------------------------------------ setup
+void Solver::finish_level(int l) {
+  Level &L = *lev[l];
+  if (l > 0 || pattern_dirty) {
+    L.diagpos.alloc(L.n);
+    reset_flags();
+    launch_diagpos(L.n, L.rowptr.p, L.col.p, L.diagpos.p, flags.p + kFDiagMissing, st);
+    MG_REQUIRE(read_flag(kFDiagMissing) == 0, MGPBD_E_INVALID_ARG,
+               "level " + std::to_string(l) + " has a row without a diagonal entry");
+    L.lanes = lanes_for_rowlen(L.n ? (double)L.nnz / (double)L.n : 1.0);
+    if (l == 0) pattern_dirty = false;
+  }
+  L.diag.alloc(L.n);
+  L.dinv.alloc(L.n);
+  if (mixed()) L.dinv32.alloc(L.n);
+  reset_flags();
+  launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, mixed() ? L.dinv32.p : nullptr,
+                      flags.p + kFBadDiag, st);
+  MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN,
+             "level " + std::to_string(l) + " has a non-positive diagonal entry");
+  // vectors of the V-cycle
+  L.r.alloc(L.n); L.z.alloc(L.n); L.t.alloc(L.n); L.res.alloc(L.n);
+  if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); L.res32.alloc(L.n); }
+  power_omega(l);
+}
+
+// omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min), lambda_max by the
+// power method and a Rayleigh quotient (Sec. 4.5)
+void Solver::power_omega(int l) {
+  Level &L = *lev[l];
+  if (L.n == 0) { L.omega = 0.0; return; }
+  uint64_t salt = stream_salt(opt.seed, kStreamPowerStart);
+  double *v = L.r.p, *w = L.t.p;
+  launch_pow_init(L.n, salt, l, v, st);
+  CsrView<double> A = L.view();
+  for (int it = 0; it < opt.power_iters; ++it) {
+    launch_spmv<double>(A, v, w, st);
+    launch_pow_scale(L.n, w, L.diag.p, dscal.p, rb(), st);
+    launch_pow_normalize(L.n, w, dscal.p, v, st);
+  }
+  launch_spmv<double>(A, v, w, st);
+  launch_rayleigh(L.n, v, w, L.diag.p, dscal.p + 1, rb(), st);
+  double *h = static_cast<double *>(pinned);
+  MG_HIP(hipMemcpyAsync(h, dscal.p + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  double lmax = h[0] / h[1];
+  L.omega = 2.0 / (opt.lmax_scale * lmax + opt.lambda_min);
+}
+
+void Solver::aggregate(int l) {
+  Level &L = *lev[l];
+  const int64_t n = L.n;
+  CsrView<double> A = L.view();
+  strong.reserve(L.nnz);
+  conn.reserve(n);
+  key.reserve(n);
+  m1.reserve(n);
+  const double theta2 = opt.theta * opt.theta;
+  launch_strong(A, L.diag.p, theta2, strong.p, conn.p, st);
+  launch_mis_init(n, conn.p, stream_salt(opt.seed, kStreamAggPrio), l, key.p, st);
+  for (int round = 0;; ++round) {
+    MG_REQUIRE(round < 100000, MGPBD_E_SETUP, "aggregation did not terminate");
+    reset_flags();
+    launch_mis_round(A, strong.p, key.p, m1.p, flags.p + kFUndecided, st);
+    if (read_flag(kFUndecided) == 0) break;
+  }
+  itmp.reserve(n);
+  ltmp.reserve(n + 1);
+  launch_root_flags(n, key.p, itmp.p, st);
+  scan_exclusive_i32_to_i64(itmp.p, ltmp.p, n, scan_tmp, st);
+  L.n_agg = read_dev(ltmp.p + n, st, pinned);
+  L.agg.alloc(n);
+  itmp2.reserve(n);
+  launch_pass1(A, strong.p, key.p, ltmp.p, itmp2.p, st);
+  launch_pass2(A, strong.p, conn.p, itmp2.p, L.agg.p, st);
+}
+
+// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|),
+// then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
+void Solver::candidate0() {
+  Level &L = *lev[0];
+  const int64_t n = L.n;
+  L.B.alloc(n);
+  if (opt.b_mode == 1) {
+    launch_fill(n, 1.0, L.B.p, st);
+    return;
+  }
+  CsrView<double> A = L.view();
+  MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long), st));
+  launch_absmax(L.nnz, L.val.p, amax.p, st);
+  launch_candidate_init(n, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
+  // greedy colouring (Jones-Plassmann rounds)
+  key.reserve(n);
+  L.color.alloc(n);
+  launch_color_keys(n, stream_salt(opt.seed, kStreamColorPrio), key.p, st);
+  launch_fill_i32(n, -1, L.color.p, st);
+  for (int round = 0;; ++round) {
+    MG_REQUIRE(round < 1000000, MGPBD_E_SETUP, "colouring did not terminate");
+    reset_flags();
+    launch_color_round(A, key.p, L.color.p, flags.p + kFRemaining, flags.p + kFColorOver, st);
+    int *h = static_cast<int *>(pinned);
+    MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    MG_REQUIRE(h[kFColorOver] == 0, MGPBD_E_SETUP, "more than 256 colours needed");
+    if (h[kFRemaining] == 0) break;
+  }
+  // rows grouped by colour
+  itmp.reserve(256);
+  MG_HIP(hipMemsetAsync(itmp.p, 0, 256 * sizeof(int32_t), st));
+  launch_count_colors(n, L.color.p, itmp.p, st);
+  std::vector<int32_t> cnt(256);
+  MG_HIP(hipMemcpyAsync(cnt.data(), itmp.p, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  L.n_colors = 0;
+  for (int c = 0; c < 256; ++c) if (cnt[c]) L.n_colors = c + 1;
+  L.color_off.assign(L.n_colors + 1, 0);
+  for (int c = 0; c < L.n_colors; ++c) L.color_off[c + 1] = L.color_off[c] + cnt[c];
+  ltmp2.reserve(257);
+  MG_HIP(hipMemcpyAsync(ltmp2.p, L.color_off.data(), sizeof(int64_t) * (L.n_colors + 1),
+                        hipMemcpyHostToDevice, st));
+  MG_HIP(hipMemsetAsync(itmp.p, 0, 256 * sizeof(int32_t), st));
+  L.color_rows.alloc(n);
+  launch_scatter_colors(n, L.color.p, ltmp2.p, itmp.p, L.color_rows.p, st);
+  for (int s = 0; s < opt.gs_sweeps; ++s)
+    for (int c = 0; c < L.n_colors; ++c)
+      launch_gs_color(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
+                      L.diag.p, L.B.p, st);
+}
+
+void Solver::build_members(int l) {
+  Level &L = *lev[l];
+  const int64_t na = L.n_agg;
+  itmp.reserve(std::max<int64_t>(na, 1));
+  MG_HIP(hipMemsetAsync(itmp.p, 0, sizeof(int32_t) * na, st));
+  launch_count_members(L.n, L.agg.p, itmp.p, st);
+  L.agg_ptr.alloc(na + 1);
+  scan_exclusive_i32_to_i64(itmp.p, L.agg_ptr.p, na, scan_tmp, st);
+  MG_HIP(hipMemsetAsync(itmp.p, 0, sizeof(int32_t) * na, st));
+  int64_t nmem = read_dev(L.agg_ptr.p + na, st, pinned);
+  L.agg_mem.alloc(std::max<int64_t>(nmem, 1));
+  launch_scatter_members(L.n, L.agg.p, L.agg_ptr.p, itmp.p, L.agg_mem.p, st);
+  launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
+}
+
+void Solver::galerkin_symbolic(int l) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  const int64_t na = L.n_agg;
+  CsrView<double> A = L.view();
+  ltmp.reserve(na + 1);
+  ltmp2.reserve(na + 1);
+  reset_flags();
+  launch_gal_count(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, ltmp.p, ltmp2.p,
+                   flags.p + kFOverflow, st);
+  MG_REQUIRE(read_flag(kFOverflow) == 0, MGPBD_E_SETUP,
+             "a coarse row has more distinct columns than the symbolic table holds");
+  C.n = na;
+  C.rowptr.alloc(na + 1);
+  scan_exclusive_i64(ltmp.p, C.rowptr.p, na, scan_tmp, st);
+  DevBuf<int64_t> eoff;
+  eoff.alloc(na + 1);
+  scan_exclusive_i64(ltmp2.p, eoff.p, na, scan_tmp, st);
+  C.nnz = read_dev(C.rowptr.p + na, st, pinned);
+  int64_t nlist = read_dev(eoff.p + na, st, pinned);
+  MG_REQUIRE(nlist < (int64_t)INT32_MAX * 2, MGPBD_E_SETUP, "Galerkin list too long");
+  C.col.alloc(C.nnz);
+  C.crow.alloc(C.nnz);
+  C.mirror.alloc(C.nnz);
+  L.gl_ptr.alloc(C.nnz + 1);
+  L.gl_idx.alloc(std::max<int64_t>(nlist, 1));
+  L.gl_row.alloc(std::max<int64_t>(nlist, 1));
+  reset_flags();
+  launch_gal_fill(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, C.rowptr.p, eoff.p, C.col.p, C.crow.p,
+                  L.gl_ptr.p, L.gl_idx.p, L.gl_row.p, flags.p + kFOverflow, st);
+  MG_HIP(hipMemcpyAsync(L.gl_ptr.p + C.nnz, eoff.p + na, sizeof(int64_t),
+                        hipMemcpyDeviceToDevice, st));
+  launch_gal_mirror(C.nnz, C.crow.p, C.col.p, C.rowptr.p, C.mirror.p, flags.p + kFMirror, st);
+  int *h = static_cast<int *>(pinned);
+  MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  MG_REQUIRE(h[kFOverflow] == 0, MGPBD_E_SETUP, "symbolic Galerkin table overflow");
+  MG_REQUIRE(h[kFMirror] == 0, MGPBD_E_SETUP, "coarse pattern is not symmetric");
+  C.val.alloc(C.nnz);
+  if (mixed()) C.val32.alloc(C.nnz);
+}
+
+void Solver::galerkin_numeric(int l) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  launch_gal_numeric(C.nnz, C.crow.p, C.col.p, C.mirror.p, L.gl_ptr.p, L.gl_idx.p, L.gl_row.p,
+                     L.col.p, L.val.p, L.p.p, C.val.p, mixed() ? C.val32.p : nullptr, st);
+}
+
+void Solver::factor_last() {
+  Level &L = *lev[nlev - 1];
+  nd = L.n;
+  int64_t np = (nd + 15) / 16 * 16;
+  dense.reserve(std::max<int64_t>(nd * nd, 1));
+  dscratch.reserve(std::max<int64_t>(2 * np * np, 1));
+  Ainv.reserve(std::max<int64_t>(nd * nd, 1));
+  launch_csr_to_dense(nd, L.rowptr.p, L.col.p, L.val.p, dense.p, st);
+  reset_flags();
+  launch_chol_inverse(nd, dense.p, dscratch.p, Ainv.p, flags.p + kFChol, st);
+  MG_REQUIRE(read_flag(kFChol) == 0, MGPBD_E_BREAKDOWN,
+             "coarsest level is not positive definite");
+}
+
+void Solver::setup() {
+  invalidate_graph();
+  built = false;
+  while (lev.size() > 1) lev.pop_back();
+  Level &F = *lev[0];
+  F.has_next = false;
+  F.n_agg = 0;
+  MG_REQUIRE(opt.max_levels >= 1 && opt.max_levels <= 32, MGPBD_E_INVALID_ARG,
+             "max_levels must be in 1..32");
+  if (mixed() && !val32_external) {
+    F.val32.alloc(F.nnz);
+    launch_d2f(F.nnz, F.val.p, F.val32.p, nullptr, st);
+  }
+  bool force_last = false, stalled = false;
+  nlev = 1;
+  for (int l = 0;; ++l) {
+    Level &L = *lev[l];
+    nlev = l + 1;
+    finish_level(l);
+    if (force_last || L.n <= opt.coarse_max || nlev >= opt.max_levels) break;
+    aggregate(l);
+    if (L.n_agg == 0) break;
+    if (l == 0) candidate0();
+    build_members(l);
+    lev.emplace_back(new Level());
+    Level &C = *lev[l + 1];
+    L.p.alloc(L.n);
+    if (mixed()) L.p32.alloc(L.n);
+    launch_fill(L.n, 0.0, L.p.p, st);
+    C.B.alloc(L.n_agg);
+    launch_normalize(L.n_agg, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.p.p, mixed() ? L.p32.p : nullptr,
+                     C.B.p, st);
+    if (mixed()) launch_d2f(L.n, L.p.p, L.p32.p, nullptr, st);
+    galerkin_symbolic(l);
+    galerkin_numeric(l);
+    L.has_next = true;
+    if ((double)L.n_agg > 0.95 * (double)L.n) force_last = stalled = true;
+  }
+  Level &last = *lev[nlev - 1];
+  if (last.n <= opt.dense_max) {
+    last_dense = true;
+    factor_last();
+  } else if (!stalled) {
+    last_dense = false;  // every row isolated or the level cap: smoothing only
+  } else {
+    throw Error(MGPBD_E_SETUP, "coarsening stalled with " + std::to_string(last.n) +
+                                   " rows above dense_max");
+  }
+  ensure_vectors();
+  built = true;
+}
+
+void Solver::refresh() {
+  MG_REQUIRE(built, MGPBD_E_STATE, "refresh without a hierarchy");
+  Level &F = *lev[0];
+  if (mixed() && !val32_external) launch_d2f(F.nnz, F.val.p, F.val32.p, nullptr, st);
+  for (int l = 0; l + 1 < nlev; ++l) galerkin_numeric(l);
+  reset_flags();
+  for (int l = 0; l < nlev; ++l) {
+    Level &L = *lev[l];
+    launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p,
+                        mixed() ? L.dinv32.p : nullptr, flags.p + kFBadDiag, st);
+  }
+  MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN, "non-positive diagonal entry");
+  if (last_dense) factor_last();
+}
+
+void Solver::ensure_vectors() {
+  const int64_t n = lev[0]->n;
+  x.reserve(n); r.reserve(n); z.reserve(n); p.reserve(n); q.reserve(n);
+  if (opt.precision == MGPBD_PREC_MIXED) zold.reserve(n);
+}
+
+// ------------------------------------------------------------ V-cycle
+template <class T> struct Buf;
+template <> struct Buf<double> {
+  static DevBuf<double> &z(Level &L) { return L.z; }
+  static DevBuf<double> &t(Level &L) { return L.t; }
+  static DevBuf<double> &r(Level &L) { return L.r; }
+  static DevBuf<double> &res(Level &L) { return L.res; }
+  static CsrView<double> A(const Level &L) { return L.view(); }
+  static const double *dinv(const Level &L) { return L.dinv.p; }
+  static const double *p(const Level &L) { return L.p.p; }
+};
+template <> struct Buf<float> {
+  static DevBuf<float> &z(Level &L) { return L.z32; }
+  static DevBuf<float> &t(Level &L) { return L.t32; }
+  static DevBuf<float> &r(Level &L) { return L.r32; }
+  static DevBuf<float> &res(Level &L) { return L.res32; }
+  static CsrView<float> A(const Level &L) { return L.view32(); }
+  static const float *dinv(const Level &L) { return L.dinv32.p; }
+  static const float *p(const Level &L) { return L.p32.p; }
+};
+
+// `sweeps` omega-Jacobi sweeps; from_zero: the iterate starts at 0 (the
+// first sweep is z = omega D^-1 r, the first two are fused in one pass)
+template <class T>
+void Solver::smooth(Level &L, const T *r, T *&a, T *&b, int sweeps, bool from_zero) {
+  const int *done = done_ptr();
+  CsrView<T> A = Buf<T>::A(L);
+  const T *dinv = Buf<T>::dinv(L);
+  const T om = (T)L.omega;
+  int k = 0;
+  if (from_zero) {
+    if (sweeps >= 2) { launch_jacobi_first2<T>(A, dinv, r, om, a, done, st); k = 2; }
+    else if (sweeps == 1) { launch_jacobi_first<T>(L.n, dinv, r, om, a, done, st); k = 1; }
+    else { launch_zero_t<T>(L.n, a, done, st); }
+  }
+  for (; k < sweeps; ++k) {
+    launch_jacobi<T>(A, dinv, r, om, a, b, done, st);
+    std::swap(a, b);
+  }
+}
+
+template <class T>
+void Solver::vcycle(int l, const T *r, T *z) {
+  Level &L = *lev[l];
+  const int *done = done_ptr();
+  if (l == nlev - 1 && last_dense) {
+    launch_dense_apply<T>(L.n, Ainv.p, r, z, done, st);
+    return;
+  }
+  T *a = z, *b = Buf<T>::t(L).p;
+  smooth<T>(L, r, a, b, opt.pre_sweeps, true);
+  if (l + 1 < nlev) {
+    Level &C = *lev[l + 1];
+    T *res = Buf<T>::res(L).p;
+    launch_residual<T>(Buf<T>::A(L), r, a, res, done, st);
+    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, Buf<T>::r(C).p, done, st);
+    vcycle<T>(l + 1, Buf<T>::r(C).p, Buf<T>::z(C).p);
+    launch_prolong<T>(L.n, L.agg.p, Buf<T>::p(L), Buf<T>::z(C).p, a, done, st);
+  }
+  smooth<T>(L, r, a, b, opt.post_sweeps, false);
+  if (a != z) launch_copy_t<T>(L.n, a, z, done, st);
+}
+
+void Solver::apply_vcycle(const double *rin, double *zout) {
+  if (mixed()) {
+    Level &F = *lev[0];
+    launch_d2f(F.n, rin, F.r32.p, done_ptr(), st);
+    vcycle<float>(0, F.r32.p, F.z32.p);
+    launch_f2d(F.n, F.z32.p, zout, done_ptr(), st);
+  } else {
+    vcycle<double>(0, rin, zout);
+  }
+}
+
+// ------------------------------------------------------------ PCG
+void Solver::iterate_once(int k) {
+  Level &F = *lev[0];
+  const int64_t n = F.n;
+  const bool flex = mixed();
+  // external event nodes: valid inside a captured graph and on a plain stream
+  if (opt.profile_spmv) MG_HIP(hipEventRecordWithFlags(ev[2 * k], st, hipEventRecordExternal));
+  launch_pcg_spmv_dot(ctl.p, F.view(), p.p, q.p, rb(), st);
+  if (opt.profile_spmv) MG_HIP(hipEventRecordWithFlags(ev[2 * k + 1], st, hipEventRecordExternal));
+  launch_pcg_update(ctl.p, n, p.p, q.p, x.p, r.p, rb(), st);
+  if (flex) {
+    launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
+    vcycle<float>(0, F.r32.p, F.z32.p);
+    launch_pcg_rz(ctl.p, n, r.p, z.p, F.z32.p, zold.p, true, rb(), st);
+  } else {
+    vcycle<double>(0, r.p, z.p);
+    launch_pcg_rz(ctl.p, n, r.p, z.p, nullptr, zold.p, false, rb(), st);
+  }
+  launch_pcg_pupdate(ctl.p, n, z.p, p.p, st);
+}
+
+PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters, int force) {
+  MG_REQUIRE(built, MGPBD_E_STATE, "solve without a hierarchy");
+  Level &F = *lev[0];
+  const int64_t n = F.n;
+  ensure_vectors();
+  PcgCtl h{};
+  h.done = 0;
+  h.iters = 0;
+  h.force = force;
+  h.max_iters = max_iters;
+  h.tol = tol;
+  PcgCtl *hp = static_cast<PcgCtl *>(pinned);
+  *hp = h;
+  MG_HIP(hipMemcpyAsync(ctl.p, hp, sizeof(PcgCtl), hipMemcpyHostToDevice, st));
+  launch_pcg_init(ctl.p, n, b, x.p, r.p, rb(), st);
+  apply_vcycle(r.p, z.p);
+  launch_pcg_init_p(ctl.p, n, r.p, z.p, p.p, zold.p, mixed(), rb(), st);
+  const int chunk = std::max(1, opt.check_every);
+  const bool use_graph = opt.use_graph && st != nullptr;
+  if (opt.profile_spmv && (int)ev.size() < 2 * chunk) {
+    invalidate_graph();
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.assign(2 * chunk, nullptr);
+    for (auto &e : ev) MG_HIP(hipEventCreate(&e));
+  }
+  if (use_graph && !graph_ok) {
+    invalidate_graph();
+    MG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int k = 0; k < chunk; ++k) iterate_once(k);
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(st, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      throw;
+    }
+    MG_HIP(hipStreamEndCapture(st, &graph));
+    MG_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    graph_ok = true;
+  }
+  int launched = 0;
+  while (true) {
+    // the control block tells whether the solve already ended
+    MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    if (hp->done || launched >= max_iters) break;
+    int before = hp->iters;
+    if (use_graph) {
+      MG_HIP(hipGraphLaunch(gexec, st));
+    } else {
+      for (int k = 0; k < chunk; ++k) iterate_once(k);
+    }
+    launched += chunk;
+    if (opt.profile_spmv) {
+      MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl), hipMemcpyDeviceToHost, st));
+      MG_HIP(hipStreamSynchronize(st));
+      int ran = std::min(chunk, hp->iters - before + (hp->done == 2 ? 1 : 0));
+      for (int k = 0; k < ran; ++k) {
+        float ms = 0.f;
+        MG_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        spmv_ms += ms;
+        ++spmv_calls;
+      }
+    }
+  }
+  if (x_out != x.p) launch_copy(n, x.p, x_out, nullptr, st);
+  PcgResult res;
+  res.status = hp->done;
+  res.iters = hp->iters;
+  res.ratio = hp->ratio;
+  res.bnorm = hp->bnorm;
+  if (res.status == 0) res.status = 4;
+  return res;
+}
+
+template void Solver::vcycle<double>(int, const double *, double *);
+template void Solver::vcycle<float>(int, const float *, float *);
+
+}  // namespace mgpbd

@@ -1,0 +1,141 @@
+// AMG hierarchy (setup phase, Sec. 4.1-4.3, 4.5) and MGPCG solve (Sec. 4.4)
+// on one GPU. The host sequences kernels; all data stays in device memory.
+#pragma once
+
+#include <memory>
+
+#include "setup.hpp"
+
+namespace mgpbd {
+
+struct Level {
+  int64_t n = 0, nnz = 0;
+  int lanes = 16;
+  double omega = 0.0;
+  DevBuf<int64_t> rowptr;
+  DevBuf<int32_t> col;
+  DevBuf<double> val;
+  DevBuf<float> val32;
+  DevBuf<int64_t> diagpos;
+  DevBuf<double> diag, dinv;
+  DevBuf<float> dinv32;
+  // entries of this (coarse) level: row of each entry and its transpose position
+  DevBuf<int32_t> crow, mirror;
+  // transfer to the next level
+  bool has_next = false;
+  int64_t n_agg = 0;
+  DevBuf<int32_t> agg;
+  DevBuf<int64_t> agg_ptr;
+  DevBuf<int32_t> agg_mem;
+  DevBuf<double> p, B;
+  DevBuf<float> p32;
+  // fine entries feeding each entry of the next level, ascending fine order
+  DevBuf<int64_t> gl_ptr;
+  DevBuf<int32_t> gl_idx, gl_row;
+  // multicolour order (level 0 near-kernel sweeps)
+  int n_colors = 0;
+  std::vector<int64_t> color_off;
+  DevBuf<int32_t> color, color_rows;
+  // V-cycle vectors
+  DevBuf<double> r, z, t, res;
+  DevBuf<float> r32, z32, t32, res32;
+
+  CsrView<double> view() const {
+    CsrView<double> v;
+    v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val.p; v.lanes = lanes;
+    return v;
+  }
+  CsrView<float> view32() const {
+    CsrView<float> v;
+    v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val32.p; v.lanes = lanes;
+    return v;
+  }
+};
+
+struct PcgResult {
+  int status = 0;  // PcgCtl::done code
+  int iters = 0;
+  double ratio = 0.0;
+  double bnorm = 0.0;
+};
+
+class Solver {
+ public:
+  explicit Solver(const mgpbd_options &o);
+  ~Solver();
+
+  mgpbd_options opt;
+  hipStream_t st = nullptr;
+  std::vector<std::unique_ptr<Level>> lev;
+  int nlev = 0;
+  bool last_dense = false;
+  bool built = false;
+  bool val32_external = false;  // level-0 FP32 values written by the assembler
+  bool pattern_dirty = true;    // level-0 pattern changed: recompute diagpos/lanes
+
+  // per-iteration profiling of the fine-level A p product
+  int64_t spmv_calls = 0;
+  double spmv_ms = 0.0;
+
+  Level &L0() { return *lev[0]; }
+  bool mixed() const { return opt.precision == MGPBD_PREC_MIXED; }
+  void set_stream(hipStream_t s);
+  void invalidate_graph();
+
+  // Full setup on the current level-0 values (aggregation, candidates, P,
+  // Galerkin pattern and values, omega, coarsest inverse).
+  void setup();
+  // Solving-phase refresh for new level-0 values with the kept P and omega.
+  void refresh();
+  // MGPCG on A_0: x_out (device, may be the internal iterate) <- A_0^-1 b
+  PcgResult pcg(const double *b, double *x_out, double tol, int max_iters, int force);
+  // one preconditioner application z = V(r) (FP64 interface)
+  void apply_vcycle(const double *r, double *z);
+
+  double *dl() { return x.p; }   // internal PCG iterate
+  // sum of squares of a device vector (deterministic), synchronous
+  double norm2(const double *v, int64_t n);
+
+ private:
+  // device scratch
+  DevBuf<PcgCtl> ctl;
+  DevBuf<double> red_partials;
+  DevBuf<unsigned> red_ticket;
+  DevBuf<double> x, r, z, p, q, zold;
+  DevBuf<double> dscal;
+  DevBuf<int> flags;
+  DevBuf<unsigned long long> amax;
+  DevBuf<int64_t> scan_tmp;
+  DevBuf<uint8_t> strong, conn;
+  DevBuf<uint64_t> key, m1;
+  DevBuf<int32_t> itmp, itmp2;
+  DevBuf<int64_t> ltmp, ltmp2;
+  DevBuf<double> dense, dscratch, Ainv;
+  int64_t nd = 0;
+  // pinned host staging
+  void *pinned = nullptr;
+  // graph of check_every PCG iterations
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ok = false;
+  std::vector<hipEvent_t> ev;
+
+  RedBuf rb() { return RedBuf{red_partials.p, red_ticket.p}; }
+  const int *done_ptr() const;
+  int read_flag(int k);
+  void reset_flags();
+  void ensure_vectors();
+  void finish_level(int l);
+  void aggregate(int l);
+  void candidate0();
+  void build_members(int l);
+  void galerkin_symbolic(int l);
+  void galerkin_numeric(int l);
+  void power_omega(int l);
+  void factor_last();
+  void iterate_once(int k);
+  template <class T> void vcycle(int l, const T *r, T *z);
+  template <class T> void smooth(Level &L, const T *r, T *&a, T *&b, int sweeps, bool from_zero);
+};
+
+}  // namespace mgpbd

@@ -1,0 +1,45 @@
+// Launchers of the simulation-loop kernels (Algorithm 1) and host-side
+// construction of the fixed pattern of A.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mgpbd {
+
+void launch_predict(int64_t nv, const double *w, const double *g, double dt, double *const *xyz,
+                    double *const *vxyz, double *const *oxyz, hipStream_t s);
+void launch_constraints(int64_t m, int64_t n_edges, const int32_t *rv, const double *rest_c,
+                        const double *const *xyz, double *C, double *grad, hipStream_t s);
+void launch_assemble(int64_t m, int64_t n_edges, int lanes, const int64_t *rp, const int32_t *col,
+                     const uint32_t *meta, const int32_t *rv, const double *w, const double *grad,
+                     const double *alpha_t, const double *C, const double *lambda, double *val,
+                     float *val32, double *b, hipStream_t s);
+void launch_dx_update(int64_t nv, const int64_t *vptr, const int32_t *vrow, const int8_t *vslot,
+                      const double *grad, const double *dl, const double *w, double omega,
+                      double *const *xyz, hipStream_t s);
+void launch_lambda_add(int64_t m, double *lambda, const double *dl, hipStream_t s);
+void launch_velocity(int64_t nv, double dt, double *const *xyz, double *const *oxyz,
+                     double *const *vxyz, hipStream_t s);
+void launch_check_finite(int64_t n, const double *a, int *bad, hipStream_t s);
+void launch_sqrt_div(int64_t n, const double *a, const double *b, double *s, double *q,
+                     hipStream_t st);
+
+// Host-built topology: rows (edges then volumes), the pattern of A (pairs of
+// rows sharing a vertex, sorted columns) with per-entry shared-vertex codes,
+// and the vertex -> (row, slot) incidence used by the dx gather.
+struct Topology {
+  int64_t n_verts = 0, n_edges = 0, n_vols = 0, m = 0, nnz = 0;
+  std::vector<int32_t> rv;       // [m][4], -1 padded
+  std::vector<int64_t> rowptr;   // [m + 1]
+  std::vector<int32_t> col;      // [nnz]
+  std::vector<uint32_t> meta;    // [nnz]
+  std::vector<int64_t> vptr;     // [n_verts + 1]
+  std::vector<int32_t> vrow;     // rows containing each vertex, ascending
+  std::vector<int8_t> vslot;     // local slot of the vertex in that row
+};
+
+// Validates indices and ordering (throws Error(MGPBD_E_INVALID_ARG)).
+void build_topology(int64_t n_verts, int64_t n_tets, const int32_t *tets, int64_t n_edges,
+                    const int32_t *edges, int64_t n_vols, const int32_t *vol_tet, Topology &t);
+
+}  // namespace mgpbd

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs. Integer and index results (pattern, aggregates,
+colours) must be bit-exact; the setup is a pure function of the bits of A,
+so the FP64 values that feed it (A, candidates, P, Galerkin products) are
+compared bitwise too; positions must agree within 1e-9 relative (FP64)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2505_13390_amd import workloads as W
+from tests.gpu_common import B, log, opts, rel_pos_err, run_both
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    yield
+
+
+def test_device_sqrt_and_division_are_correctly_rounded():
+    rng = np.random.default_rng(0)
+    n = 1 << 20
+    a = np.abs(rng.standard_normal(n)) * np.exp2(rng.integers(-300, 300, n).astype(float))
+    b = rng.standard_normal(n) * np.exp2(rng.integers(-300, 300, n).astype(float))
+    special = np.array([1.0, 2.0, 3.0, 4.0, 0.25, 1e-310, 5e-324, 1.7976931348623157e308,
+                        0.0, 9007199254740993.0, 1.0000000000000002, 0.9999999999999999])
+    a[:special.size] = special
+    b[:special.size] = special[::-1] + 1.0
+    ta = torch.tensor(a, device="cuda")
+    tb = torch.tensor(b, device="cuda")
+    s, q = B.mgpbd_selftest_sqrt_div(ta, tb)
+    s, q = s.cpu().numpy(), q.cpu().numpy()
+    assert np.array_equal(s.view(np.uint64), np.sqrt(a).view(np.uint64))
+    assert np.array_equal(q.view(np.uint64), (a / b).view(np.uint64))
+
+
+def compare_hierarchy(sim, body, what):
+    """Bit-exact comparison of the setup built by both sides."""
+    h = sim.hier()
+    L = B.mgpbd_num_levels(body.ctx)
+    log(what, "levels oracle", h.levels, "gpu", L)
+    assert L == h.levels
+    for l in range(L):
+        gi = B.mgpbd_get_level(body.ctx, l)
+        oi = h.info(l)
+        log("  level", l, "n", gi["n"], "nnz", gi["nnz"], "omega gpu %.12g oracle %.12g"
+            % (gi["omega"], oi["omega"]))
+        assert gi["n"] == oi["n"] and gi["nnz"] == oi["nnz"]
+        grp, gcol, gval = B.mgpbd_get_matrix(body.ctx, l)
+        orp, ocol, oval = h.matrix(l)
+        assert np.array_equal(grp, orp) and np.array_equal(gcol, ocol)
+        nbad = int((gval.view(np.uint64) != oval.view(np.uint64)).sum())
+        assert nbad == 0, "level %d: %d matrix values differ" % (l, nbad)
+        if oi["omega"] > 0:
+            assert abs(gi["omega"] - oi["omega"]) <= 1e-9 * oi["omega"]
+        if l + 1 < L:
+            assert gi["n_agg"] == h.info(l + 1)["n"]
+            gagg = B.mgpbd_get_aggregates(body.ctx, l)
+            oagg, op, oB = h.transfer(l)
+            assert np.array_equal(gagg, oagg), "level %d aggregates differ" % l
+            gp, gB = B.mgpbd_get_transfer(body.ctx, l)
+            assert np.array_equal(gB.view(np.uint64), oB.view(np.uint64)), "candidate differs"
+            assert np.array_equal(gp.view(np.uint64), op.view(np.uint64)), "P differs"
+    oc, onc = h.colors()
+    gc, gnc = B.mgpbd_get_colors(body.ctx, sim.m)
+    assert gnc == onc and np.array_equal(gc, oc)
+
+
+def test_c0_first_iteration_assembly_and_setup_bit_exact():
+    w = W.beam_c0()
+    log("C0 rows", w.n_rows)
+    sim, body, pos, vel, ores, gres = run_both(w, 1)
+    # A pattern and values at iteration 0 (same predicted positions)
+    orp, ocol = sim.pattern()
+    grp, gcol, gval = B.mgpbd_get_matrix(body.ctx, 0)
+    assert np.array_equal(grp, orp) and np.array_equal(gcol, ocol)
+    assert np.array_equal(gval.view(np.uint64), sim.matrix_values().view(np.uint64))
+    assert np.array_equal(B.mgpbd_get_rhs(body.ctx, sim.m).view(np.uint64),
+                          sim.rhs().view(np.uint64))
+    compare_hierarchy(sim, body, "C0")
+    log("pcg iters oracle", ores[0]["pcg_iters"], "gpu", gres[0]["pcg_iters"])
+    assert abs(int(ores[0]["pcg_iters"][0]) - int(gres[0]["pcg_iters"][0])) <= 3
+    err = rel_pos_err(body.positions(), pos)
+    log("C0 1-iteration position error", err)
+    assert err <= 1e-9
+
+
+def test_c0_frame_positions_within_1e9():
+    w = W.beam_c0()
+    sim, body, pos, vel, ores, gres = run_both(w, 20)
+    log("oracle iters", ores[0]["pcg_iters"].tolist())
+    log("gpu    iters", gres[0]["pcg_iters"].tolist())
+    err = rel_pos_err(body.positions(), pos)
+    verr = float(np.abs(body.velocities() - vel).max() / max(np.abs(vel).max(), 1e-300))
+    lerr = float(np.abs(B.mgpbd_get_lambda(body.ctx, sim.m) - sim.lam()).max()
+                 / np.abs(sim.lam()).max())
+    log("C0 frame: position err %.3e velocity err %.3e lambda err %.3e" % (err, verr, lerr))
+    assert err <= 1e-9
+    assert (gres[0]["pcg_ratio"] <= 1e-6).all()
+
+
+def test_c0_frame_with_forced_pcg_counts():
+    """Parity mode: both sides run exactly the oracle's PCG iteration counts."""
+    w = W.beam_c0()
+    sim, body, pos, vel, ores, gres = run_both(w, 20, force_from_oracle=True)
+    assert (gres[0]["pcg_iters"] == ores[0]["pcg_iters"]).all()
+    err = rel_pos_err(body.positions(), pos)
+    log("C0 forced-count position error %.3e" % err)
+    assert err <= 1e-9
+
+
+def test_graph_and_direct_launch_are_bitwise_identical():
+    w = W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8)
+    res = []
+    for g in (1, 0, 1):
+        _, go = opts(use_graph=g, coarse_max=60)
+        body = B.Body(w, go)
+        body.step(4)
+        res.append(body.positions())
+        body.close()
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+
+
+@pytest.mark.parametrize("dims,vols,cmax", [((1, 1, 1), False, 400), ((2, 1, 1), True, 400),
+                                            ((5, 3, 2), True, 40), ((9, 2, 3), True, 25),
+                                            ((16, 4, 4), True, 400), ((20, 6, 5), False, 120)])
+def test_small_and_ragged_meshes(dims, vols, cmax):
+    w = W.tiny_beam(*dims, volumes=vols, alpha_edge=1e-7, alpha_vol=1e-8)
+    log("mesh", dims, "rows", w.n_rows)
+    sim, body, pos, vel, ores, gres = run_both(w, 5, coarse_max=cmax)
+    compare_hierarchy(sim, body, str(dims))
+    err = rel_pos_err(body.positions(), pos)
+    log("  position error %.3e" % err, "iters", ores[0]["pcg_iters"].tolist(),
+        gres[0]["pcg_iters"].tolist())
+    assert err <= 1e-9
+
+
+def test_lazy_setup_schedule_and_parity_over_frames():
+    w = W.tiny_beam(16, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-9)
+    sim, body, pos, vel, ores, gres = run_both(w, 4, frames=3, reuse_interval=2, coarse_max=80)
+    for o, g in zip(ores, gres):
+        assert (o["setup"] == g["setup_ran"]).all()
+    assert [g["setup_ran"].tolist() for g in gres] == [[1, 0, 0, 0], [0, 0, 0, 0], [1, 0, 0, 0]]
+    err = rel_pos_err(body.positions(), pos)
+    log("3 frames lazy: position error %.3e" % err)
+    assert err <= 1e-9
+
+
+def test_setup_every_iteration_mode():
+    w = W.tiny_beam(10, 3, 3, volumes=True, alpha_edge=1e-8, alpha_vol=1e-9)
+    sim, body, pos, vel, ores, gres = run_both(w, 3, reuse_interval=0, coarse_max=40)
+    assert gres[0]["setup_ran"].tolist() == [1, 1, 1]
+    compare_hierarchy(sim, body, "every-iteration")
+    assert rel_pos_err(body.positions(), pos) <= 1e-9
+
+
+def test_solve_entry_matches_oracle():
+    w = W.perturbed(W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8), 0.01)
+    sim = O.Sim(w)
+    val, b = sim.assemble(w.x0)
+    rp, col = sim.pattern()
+    oo, go = opts(coarse_max=60)
+    h = O.Hier.build(rp, col, val, oo)
+    xo, st = h.pcg(b, 1e-8, 1000)
+    ctx = B.mgpbd_solver_create(go)
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")
+    xg = torch.zeros(sim.m, dtype=torch.float64, device="cuda")
+    r = B.mgpbd_solve(ctx, dev(rp, torch.int64), dev(col, torch.int32), dev(val, torch.float64),
+                      dev(b, torch.float64), 1e-8, xg)
+    log("solve iters oracle", st["iters"], "gpu", r["iters"])
+    assert r["status"] == B.OK
+    for l in range(h.levels - 1):
+        assert np.array_equal(B.mgpbd_get_aggregates(ctx, l), h.transfer(l)[0])
+    x = xg.cpu().numpy()
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col, rp))
+    assert np.linalg.norm(A @ x - b) <= 1.01e-8 * np.linalg.norm(b) * 10
+    assert abs(r["iters"] - st["iters"]) <= 3
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+    B.mgpbd_destroy(ctx)
+
+
+def test_mixed_precision_against_fp64_oracle():
+    w = W.beam_c0()
+    oo, go = opts(precision=B.PREC_MIXED)
+    oo64, _ = opts()
+    sim = O.Sim(w, oo64)
+    pos, vel = O.positions(w)
+    ro = sim.step(pos, vel, 20)
+    body = B.Body(w, go)
+    rg = body.step(20)
+    err = rel_pos_err(body.positions(), pos)
+    log("mixed C0: position error vs FP64 oracle %.3e" % err)
+    log("iters fp64 oracle", ro["pcg_iters"].tolist())
+    log("iters mixed gpu  ", rg["pcg_iters"].tolist())
+    assert (rg["pcg_ratio"] <= 1e-6).all()
+    assert err <= 1e-7
+
+
+def test_rest_state_stays_bitwise_at_rest():
+    w = W.tiny_beam(6, 2, 2, volumes=True)
+    w.gravity = (0.0, 0.0, 0.0)
+    _, go = opts()
+    body = B.Body(w, go)
+    x0 = body.positions()
+    r = body.step(3)
+    assert np.array_equal(body.positions(), x0)
+    assert not body.velocities().any()
+    assert (r["bnorm"] == 0).all() and (r["pcg_iters"] == 0).all()
+
+
+def test_non_finite_positions_rejected_state_unchanged():
+    w = W.tiny_beam(3, 1, 1)
+    _, go = opts()
+    body = B.Body(w, go)
+    body.x[1][2] = float("nan")
+    with pytest.raises(B.MgpbdError) as e:
+        body.step(2)
+    assert e.value.status == B.E_INVALID_ARG
+    body.x[1][2] = 0.5
+    body.step(1)
+
+
+def test_create_rejects_bad_input():
+    w = W.tiny_beam(2, 1, 1)
+    _, go = opts()
+    bad = w.alpha.copy()
+    bad[0] = -1.0
+    with pytest.raises(B.MgpbdError):
+        B.mgpbd_create(w.rest, w.inv_mass, w.tets, w.edges, w.vol_tet, bad, w.dt, w.gravity, go)
+    with pytest.raises(B.MgpbdError):
+        B.mgpbd_create(w.rest, w.inv_mass, w.tets, w.edges[::-1], w.vol_tet, w.alpha, w.dt,
+                       w.gravity, go)
+    flipped = w.tets.copy()
+    flipped[:, [1, 2]] = flipped[:, [2, 1]]
+    with pytest.raises(B.MgpbdError):
+        B.mgpbd_create(w.rest, w.inv_mass, flipped, w.edges, w.vol_tet, w.alpha, w.dt,
+                       w.gravity, go)
