@@ -70,7 +70,9 @@ typedef struct {
   int32_t b_mode;       /* 0 = smoothed near-kernel candidate, 1 = all-ones candidate */
   double eps_b;         /* end the frame's loop once |b| < eps_b (Algorithm 1); 0 = never */
   int32_t precision;    /* mgpbd_precision: MGPBD_PREC_FP64 */
-  double lmax_scale;    /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.0 */
+  double lmax_scale;    /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 (the
+                           power-method estimate lies below lambda_max; the smoother
+                           needs omega lambda_max < 2 to keep the V-cycle SPD) */
   int32_t check_every;  /* PCG iterations between host reads of the convergence flag: 8 */
   int32_t use_graph;    /* capture one PCG iteration in a hipGraph and replay it: 1 */
   int32_t profile_spmv; /* time every fine-level A p product with HIP events: 0 */

@@ -76,7 +76,7 @@ typedef struct orc_opts {
   int b_mode;          /* 0 = smoothed near-kernel, 1 = all-ones candidate */
   double eps_b;        /* stop the frame loop when |b| < eps_b (0 = never) */
   int flexible;        /* 0 = Fletcher-Reeves beta, 1 = Polak-Ribiere beta */
-  double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.0 */
+  double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -97,7 +97,7 @@ void orc_default_opts(orc_opts *o) {
   o->b_mode = 0;
   o->eps_b = 0.0;
   o->flexible = 0;
-  o->lmax_scale = 1.0;
+  o->lmax_scale = 1.05;
 }
 
 /* ------------------------------------------------------------------ */

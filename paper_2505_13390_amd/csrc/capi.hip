@@ -122,7 +122,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->b_mode = 0;
   o->eps_b = 0.0;
   o->precision = MGPBD_PREC_FP64;
-  o->lmax_scale = 1.0;
+  o->lmax_scale = 1.05;
   o->check_every = 8;
   o->use_graph = 1;
   o->profile_spmv = 0;

@@ -31,7 +31,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // C(16x16 tile at r0, c0) -= A(r0.., k0..k0+kk) * B(c0.., k0..k0+kk)^T with
 // A and B row-major n x n; one wavefront, kk a multiple of 4.
 // MFMA f64 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; lane l holds D[4 (l / 16) + q][l % 16], q = 0..3.
+// and B[l / 16][l % 16]; lane l holds D[l / 16 + 4 q][l % 16], q = 0..3.
 __device__ __forceinline__ v4d mfma_tile_nt(const double *__restrict__ M, int64_t n, int64_t r0,
                                             int64_t c0, int64_t k0, int64_t kk, v4d acc) {
   const int lane = threadIdx.x & 63;
@@ -93,10 +93,10 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, dou
       int64_t r0 = t0 + ti * 16, c0 = t0 + tk * 16;
       v4d acc = {0.0, 0.0, 0.0, 0.0};
       acc = mfma_tile_nt(D, np, r0, c0, j0, 16, acc);
-      const int cc = lane & 15, rb = (lane >> 4) * 4;
+      const int cc = lane & 15, rb = lane >> 4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int64_t rr = r0 + rb + q, cl = c0 + cc;
+        int64_t rr = r0 + rb + 4 * q, cl = c0 + cc;
         if (cl <= rr) D[rr * np + cl] = D[rr * np + cl] - acc[q];
       }
     }
@@ -130,10 +130,10 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, dou
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     int64_t kstart = (ti > tk ? ti : tk) * 16;   // Z[r][k] = Y[k][r] = 0 for k < r
     acc = mfma_tile_nt(D, np, ti * 16, tk * 16, kstart, np - kstart, acc);
-    const int cc = lane & 15, rb = (lane >> 4) * 4;
+    const int cc = lane & 15, rb = lane >> 4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int64_t rr = ti * 16 + rb + q, cl = tk * 16 + cc;
+      int64_t rr = ti * 16 + rb + 4 * q, cl = tk * 16 + cc;
       if (rr < n && cl < n) Ainv[rr * n + cl] = acc[q];
     }
   }

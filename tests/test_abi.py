@@ -43,7 +43,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.theta == 0.1 and o.gs_sweeps == 20 and o.pre_sweeps == 2 and o.post_sweeps == 2
     assert o.lambda_min == 0.1 and o.coarse_max == 400 and o.power_iters == 30
     assert o.omega_relax == 0.1 and o.tol == 1e-6 and o.seed == 20250513
-    assert o.reuse_interval == 20 and o.precision == 0 and o.lmax_scale == 1.0
+    assert o.reuse_interval == 20 and o.precision == 0 and o.lmax_scale == 1.05
     assert o.use_graph == 1 and o.check_every == 8 and o.profile_spmv == 0
 
 

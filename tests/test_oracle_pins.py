@@ -383,9 +383,11 @@ def test_omega_from_power_method_bounds_lambda_max():
         A = dense(rpl, coll, vall)
         d = np.diag(A)
         lam = np.linalg.eigvalsh(A / np.sqrt(np.outer(d, d))).max()
-        est = 2 / h.info(l)["omega"] - 0.1
+        est = (2 / h.info(l)["omega"] - 0.1) / 1.05      # undo the safety scale
         assert est <= lam * (1 + 1e-12)
         assert est >= 0.95 * lam
+        # the scaled estimate keeps the smoother convergent: omega lambda_max < 2
+        assert h.info(l)["omega"] * lam < 2.0
 
 
 def chain(n):
