@@ -75,7 +75,8 @@ typedef struct {
                            needs omega lambda_max < 2 to keep the V-cycle SPD) */
   int32_t check_every;  /* PCG iterations between host reads of the convergence flag: 8 */
   int32_t use_graph;    /* capture one PCG iteration in a hipGraph and replay it: 1 */
-  int32_t profile_spmv; /* time every fine-level A p product with HIP events: 0 */
+  int32_t profile_spmv; /* time every fine-level A p product with HIP events (the PCG
+                           loop then launches kernels directly, without the graph): 0 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.

@@ -429,10 +429,9 @@ void Solver::iterate_once(int k) {
   Level &F = *lev[0];
   const int64_t n = F.n;
   const bool flex = mixed();
-  // external event nodes: valid inside a captured graph and on a plain stream
-  if (opt.profile_spmv) MG_HIP(hipEventRecordWithFlags(ev[2 * k], st, hipEventRecordExternal));
+  if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k], st));
   launch_pcg_spmv_dot(ctl.p, F.view(), p.p, q.p, rb(), st);
-  if (opt.profile_spmv) MG_HIP(hipEventRecordWithFlags(ev[2 * k + 1], st, hipEventRecordExternal));
+  if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k + 1], st));
   launch_pcg_update(ctl.p, n, p.p, q.p, x.p, r.p, rb(), st);
   if (flex) {
     launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
@@ -463,7 +462,9 @@ PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
   apply_vcycle(r.p, z.p);
   launch_pcg_init_p(ctl.p, n, r.p, z.p, p.p, zold.p, mixed(), rb(), st);
   const int chunk = std::max(1, opt.check_every);
-  const bool use_graph = opt.use_graph && st != nullptr;
+  // events around the fine-level product are recorded on the stream, so the
+  // profiled solve launches kernels directly instead of replaying the graph
+  const bool use_graph = opt.use_graph && !opt.profile_spmv && st != nullptr;
   if (opt.profile_spmv && (int)ev.size() < 2 * chunk) {
     invalidate_graph();
     for (auto e : ev) (void)hipEventDestroy(e);
