@@ -69,8 +69,12 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--reuse", type=int, default=20)
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--max-pcg", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed frames, copy a 1 GiB buffer 3 times (reference "
+                         "kernel of known size for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU layout of this solver is a design "
@@ -90,6 +94,8 @@ def main():
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   profile_spmv=0 if args.no_profile else 1)
+    if args.max_pcg:
+        opt.max_pcg = args.max_pcg
     t0 = time.perf_counter()
     body = B.Body(w, opt)
     print("created %s: %d rows, %d entries in %.1f s" % (w.name, body.m, body.nnz,
@@ -140,6 +146,14 @@ def main():
         "roofline": roof,
     }
     body.close()
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes_read"] = src.numel() * 8
+        del src, dst
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w)

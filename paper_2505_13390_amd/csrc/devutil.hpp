@@ -25,12 +25,6 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
   return v;
 }
 
-// Coherent (L1-bypassing) load of a value written by another block of the
-// same kernel before its __threadfence().
-__device__ __forceinline__ double load_agent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Logical block index that keeps consecutive chunks of work on the same XCD:
 // hardware block b runs on XCD b % 8; the 8 XCDs get contiguous ranges.
 __device__ __forceinline__ int xcd_block() {
@@ -54,17 +48,15 @@ __device__ __forceinline__ void block_range(int64_t items, int64_t &lo, int64_t 
   if (lo > items) lo = items;
 }
 
-// Deterministic grid-wide reduction of NV doubles. Every block calls
-// grid_reduce with its threads' values; it returns true in exactly one block
-// (the last to finish) with out[k] holding the grand totals in every thread.
-// The per-block sum and the final sum follow fixed trees, so the result does
-// not depend on scheduling. partials must hold NV * gridDim.x doubles; ticket
-// starts at 0 and is reset by the last block.
+// Deterministic grid-wide reductions in two kernels. The producing kernel
+// calls block_partials (fixed-tree sum per block, one partial per block); a
+// one-block finisher kernel calls sum_partials, which adds the partials in a
+// fixed order. No device-scope fence is needed inside a kernel: the kernel
+// boundary makes the partials visible (a device-scope fence inside the kernel
+// would write back the XCD's L2 from every block).
 template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], double *partials, unsigned *ticket,
-                            double (&out)[NV]) {
+__device__ void block_partials(const double (&v)[NV], double *partials) {
   __shared__ double sh[NV][kBlock / kWave];
-  __shared__ bool last;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
 #pragma unroll
@@ -80,28 +72,30 @@ __device__ bool grid_reduce(const double (&v)[NV], double *partials, unsigned *t
       for (int q = 1; q < nw; ++q) s += sh[k][q];
       partials[(size_t)k * gridDim.x + blockIdx.x] = s;
     }
-    __threadfence();
-    unsigned t = atomicAdd(ticket, 1u);
-    last = (t == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+// Called by every thread of a single block of kBlock threads; out[k] holds
+// the total of the nparts partials of value k in every thread.
+template <int NV>
+__device__ void sum_partials(const double *partials, int nparts, double (&out)[NV]) {
+  __shared__ double sh[NV][kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
-      s += load_agent(partials + (size_t)k * gridDim.x + q);
+    for (int q = threadIdx.x; q < nparts; q += blockDim.x) s += partials[(size_t)k * nparts + q];
     s = group_sum<kWave>(s);
-    __syncthreads();
     if (lane == 0) sh[k][w] = s;
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
     double tot = sh[k][0];
     for (int q = 1; q < nw; ++q) tot += sh[k][q];
     out[k] = tot;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
-  return true;
 }
 
 // PCG control block in device memory (one per solve context).

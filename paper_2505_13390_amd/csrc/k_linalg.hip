@@ -328,10 +328,11 @@ void launch_fill_u8(int64_t n, uint8_t v, uint8_t *out, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ PCG
-__global__ __launch_bounds__(kBlock) void k_pcg_init(PcgCtl *ctl, int64_t n,
-                                                     const double *__restrict__ b,
+// Each reduction is a producing kernel (block partials) followed by a
+// one-block finisher that updates the control block.
+__global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n, const double *__restrict__ b,
                                                      double *__restrict__ x,
-                                                     double *__restrict__ r, RedBuf rb) {
+                                                     double *__restrict__ r, double *partials) {
   int64_t lo, hi;
   block_range(n, lo, hi);
   double v[1] = {0.0};
@@ -341,8 +342,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgCtl *ctl, int64_t n,
     r[i] = bi;
     v[0] += bi * bi;
   }
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_init(PcgCtl *ctl, const double *partials,
+                                                     int nparts) {
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     ctl->bnorm = sqrt(tot[0]);
     ctl->iters = 0;
     ctl->ratio = 0.0;
@@ -353,15 +359,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgCtl *ctl, int64_t n,
 }
 void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double *r, RedBuf rb,
                      hipStream_t s) {
-  k_pcg_init<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, b, x, r, rb);
+  int grid = grid_for(n, kBlock);
+  k_pcg_init<<<grid, kBlock, 0, s>>>(n, b, x, r, rb.partials);
+  k_fin_init<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_init_p(PcgCtl *ctl, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pcg_init_p(const PcgCtl *ctl, int64_t n,
                                                        const double *__restrict__ r,
                                                        const double *__restrict__ z,
                                                        double *__restrict__ p,
                                                        double *__restrict__ zold, int flexible,
-                                                       RedBuf rb) {
+                                                       double *partials) {
   if (ctl->done) return;
   int64_t lo, hi;
   block_range(n, lo, hi);
@@ -372,24 +380,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init_p(PcgCtl *ctl, int64_t n,
     if (flexible) zold[i] = zi;
     v[0] += r[i] * zi;
   }
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_init_p(PcgCtl *ctl, const double *partials,
+                                                       int nparts) {
+  if (ctl->done) return;
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     ctl->rho = tot[0];
     if (!(tot[0] > 0.0)) ctl->done = 2;
   }
 }
 void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
                        double *zold, bool flexible, RedBuf rb, hipStream_t s) {
-  k_pcg_init_p<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, r, z, p, zold, flexible ? 1 : 0, rb);
+  int grid = grid_for(n, kBlock);
+  k_pcg_init_p<<<grid, kBlock, 0, s>>>(ctl, n, r, z, p, zold, flexible ? 1 : 0, rb.partials);
+  k_fin_init_p<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv_dot(PcgCtl *ctl, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv_dot(const PcgCtl *ctl, int64_t n,
                                                          const int64_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const double *__restrict__ val,
                                                          const double *__restrict__ p,
-                                                         double *__restrict__ q, RedBuf rb) {
+                                                         double *__restrict__ q,
+                                                         double *partials) {
   if (ctl->done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
@@ -405,29 +422,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_dot(PcgCtl *ctl, int64_t n,
       v[0] += p[i] * s;
     }
   }
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *partials,
+                                                   int nparts) {
+  if (ctl->done) return;
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     ctl->pq = tot[0];
-    if (!(tot[0] > 0.0) || !(ctl->rho > 0.0)) {
-      ctl->done = 2;
-    } else {
-      ctl->alpha = ctl->rho / tot[0];
-    }
+    if (!(tot[0] > 0.0) || !(ctl->rho > 0.0)) ctl->done = 2;
+    else ctl->alpha = ctl->rho / tot[0];
   }
 }
 void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
                          RedBuf rb, hipStream_t s) {
   int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_pcg_spmv_dot<G><<<grid, kBlock, 0, s>>>(ctl, A.n, A.rowptr, A.col, A.val, p, q, rb)
+#define L_(G) k_pcg_spmv_dot<G><<<grid, kBlock, 0, s>>>(ctl, A.n, A.rowptr, A.col, A.val, p, q, rb.partials)
   MG_DISPATCH_G(A.lanes, L_);
 #undef L_
+  k_fin_pq<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_update(PcgCtl *ctl, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pcg_update(const PcgCtl *ctl, int64_t n,
                                                        const double *__restrict__ p,
                                                        const double *__restrict__ q,
                                                        double *__restrict__ x,
-                                                       double *__restrict__ r, RedBuf rb) {
+                                                       double *__restrict__ r, double *partials) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
   int64_t lo, hi;
@@ -439,8 +460,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(PcgCtl *ctl, int64_t n,
     r[i] = ri;
     v[0] += ri * ri;
   }
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_update(PcgCtl *ctl, const double *partials,
+                                                       int nparts) {
+  if (ctl->done) return;
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     int it = ctl->iters + 1;
     ctl->iters = it;
     ctl->rr = tot[0];
@@ -454,15 +481,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(PcgCtl *ctl, int64_t n,
 }
 void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,
                        double *r, RedBuf rb, hipStream_t s) {
-  k_pcg_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, p, q, x, r, rb);
+  int grid = grid_for(n, kBlock);
+  k_pcg_update<<<grid, kBlock, 0, s>>>(ctl, n, p, q, x, r, rb.partials);
+  k_fin_update<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_rz(PcgCtl *ctl, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pcg_rz(const PcgCtl *ctl, int64_t n,
                                                    const double *__restrict__ r,
                                                    double *__restrict__ z,
                                                    const float *__restrict__ z32,
                                                    double *__restrict__ zold, int flexible,
-                                                   RedBuf rb) {
+                                                   double *partials) {
   if (ctl->done) return;
   int64_t lo, hi;
   block_range(n, lo, hi);
@@ -482,8 +511,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_rz(PcgCtl *ctl, int64_t n,
       zold[i] = zi;
     }
   }
+  block_partials<2>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_rz(PcgCtl *ctl, const double *partials,
+                                                   int nparts, int flexible) {
+  if (ctl->done) return;
   double tot[2];
-  if (grid_reduce<2>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<2>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     double rho_new = tot[0];
     double num = flexible ? tot[1] : rho_new;
     ctl->beta = num / ctl->rho;
@@ -493,10 +528,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_rz(PcgCtl *ctl, int64_t n,
 }
 void launch_pcg_rz(PcgCtl *ctl, int64_t n, const double *r, double *z, const float *z32,
                    double *zold, bool flexible, RedBuf rb, hipStream_t s) {
-  k_pcg_rz<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, r, z, z32, zold, flexible ? 1 : 0, rb);
+  int grid = grid_for(n, kBlock);
+  k_pcg_rz<<<grid, kBlock, 0, s>>>(ctl, n, r, z, z32, zold, flexible ? 1 : 0, rb.partials);
+  k_fin_rz<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid, flexible ? 1 : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(PcgCtl *ctl, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(const PcgCtl *ctl, int64_t n,
                                                         const double *__restrict__ z,
                                                         double *__restrict__ p) {
   if (ctl->done) return;
@@ -510,18 +547,24 @@ void launch_pcg_pupdate(PcgCtl *ctl, int64_t n, const double *z, double *p, hipS
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
-                                                const double *__restrict__ b, double *out,
-                                                RedBuf rb) {
+                                                const double *__restrict__ b, double *partials) {
   int64_t lo, hi;
   block_range(n, lo, hi);
   double v[1] = {0.0};
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v[0] += a[i] * b[i];
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_store(const double *partials, int nparts,
+                                                      double *out) {
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) *out = tot[0];
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) *out = tot[0];
 }
 void launch_dot(int64_t n, const double *a, const double *b, double *out, RedBuf rb,
                 hipStream_t s) {
-  k_dot<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, a, b, out, rb);
+  int grid = grid_for(n, kBlock);
+  k_dot<<<grid, kBlock, 0, s>>>(n, a, b, rb.partials);
+  k_fin_store<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
 }
 
 // ------------------------------------------------------------------ scan

@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_color_round(int64_t n, const int64_t
   for (int64_t base = lo; base < hi; base += R) {
     int64_t i = base + grp;
     bool ok = i < hi;
-    bool todo = ok && __hip_atomic_load(&color[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
+    bool todo = ok && color[i] < 0;
     uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
     int wait = 0, over = 0;
     if (todo) {
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_color_round(int64_t n, const int64_t
       for (int64_t e = rp[i] + sub; e < rp[i + 1]; e += G) {
         int32_t j = col[e];
         if (j == (int32_t)i || key[j] < ki) continue;
-        int32_t cj = __hip_atomic_load(&color[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t cj = color[j];   // a stale -1 only postpones this row to a later round
         if (cj < 0) { wait = 1; continue; }
         if (cj >= kMaxColors) { over = 1; continue; }
         uint64_t bit = 1ULL << (cj & 63);
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_color_round(int64_t n, const int64_t
       else if (~m2) c = 128 + __ffsll((long long)~m2) - 1;
       else if (~m3) c = 192 + __ffsll((long long)~m3) - 1;
       else { atomicExch(overflow, 1); continue; }
-      __hip_atomic_store(&color[i], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      color[i] = c;
     }
   }
 }
@@ -765,7 +765,7 @@ void launch_pow_init(int64_t n, uint64_t salt, int level, double *v, hipStream_t
 }
 __global__ __launch_bounds__(kBlock) void k_pow_scale(int64_t n, double *__restrict__ w,
                                                       const double *__restrict__ diag,
-                                                      double *out, RedBuf rb) {
+                                                      double *partials) {
   int64_t lo, hi;
   block_range(n, lo, hi);
   double v[1] = {0.0};
@@ -774,12 +774,19 @@ __global__ __launch_bounds__(kBlock) void k_pow_scale(int64_t n, double *__restr
     w[i] = wi;
     v[0] += wi * wi;
   }
+  block_partials<1>(v, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_store1(const double *partials, int nparts,
+                                                       double *out) {
   double tot[1];
-  if (grid_reduce<1>(v, rb.partials, rb.ticket, tot) && threadIdx.x == 0) *out = tot[0];
+  sum_partials<1>(partials, nparts, tot);
+  if (threadIdx.x == 0) *out = tot[0];
 }
 void launch_pow_scale(int64_t n, double *w, const double *diag, double *out, RedBuf rb,
                       hipStream_t s) {
-  k_pow_scale<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, w, diag, out, rb);
+  int grid = grid_for(n, kBlock);
+  k_pow_scale<<<grid, kBlock, 0, s>>>(n, w, diag, rb.partials);
+  k_fin_store1<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
 }
 __global__ void k_pow_normalize(int64_t n, const double *__restrict__ w, const double *nrm2,
                                 double *__restrict__ v) {
@@ -793,8 +800,8 @@ void launch_pow_normalize(int64_t n, const double *w, const double *nrm2, double
 }
 __global__ __launch_bounds__(kBlock) void k_rayleigh(int64_t n, const double *__restrict__ v,
                                                      const double *__restrict__ Av,
-                                                     const double *__restrict__ diag, double *out,
-                                                     RedBuf rb) {
+                                                     const double *__restrict__ diag,
+                                                     double *partials) {
   int64_t lo, hi;
   block_range(n, lo, hi);
   double s[2] = {0.0, 0.0};
@@ -803,15 +810,22 @@ __global__ __launch_bounds__(kBlock) void k_rayleigh(int64_t n, const double *__
     s[0] += vi * Av[i];
     s[1] += vi * diag[i] * vi;
   }
+  block_partials<2>(s, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_store2(const double *partials, int nparts,
+                                                       double *out) {
   double tot[2];
-  if (grid_reduce<2>(s, rb.partials, rb.ticket, tot) && threadIdx.x == 0) {
+  sum_partials<2>(partials, nparts, tot);
+  if (threadIdx.x == 0) {
     out[0] = tot[0];
     out[1] = tot[1];
   }
 }
 void launch_rayleigh(int64_t n, const double *v, const double *Av, const double *diag,
                      double *out, RedBuf rb, hipStream_t s) {
-  k_rayleigh<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, v, Av, diag, out, rb);
+  int grid = grid_for(n, kBlock);
+  k_rayleigh<<<grid, kBlock, 0, s>>>(n, v, Av, diag, rb.partials);
+  k_fin_store2<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
 }
 
 }  // namespace mgpbd

@@ -79,8 +79,11 @@ void Solver::finish_level(int l) {
     launch_diagpos(L.n, L.rowptr.p, L.col.p, L.diagpos.p, flags.p + kFDiagMissing, st);
     MG_REQUIRE(read_flag(kFDiagMissing) == 0, MGPBD_E_INVALID_ARG,
                "level " + std::to_string(l) + " has a row without a diagonal entry");
-    L.lanes = lanes_for_rowlen(L.n ? (double)L.nnz / (double)L.n : 1.0);
+    L.lanes = L.lanes32 = lanes_for_rowlen(L.n ? (double)L.nnz / (double)L.n : 1.0);
     if (l == 0) pattern_dirty = false;
+    L.r.alloc(L.n); L.t.alloc(L.n);
+    if (mixed()) { L.r32.alloc(L.n); L.t32.alloc(L.n); }
+    tune_lanes(l);
   }
   L.diag.alloc(L.n);
   L.dinv.alloc(L.n);
@@ -94,6 +97,49 @@ void Solver::finish_level(int l) {
   L.r.alloc(L.n); L.z.alloc(L.n); L.t.alloc(L.n); L.res.alloc(L.n);
   if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); L.res32.alloc(L.n); }
   power_omega(l);
+}
+
+// Autotuner of the row-group CSR kernels: on large levels, time one product
+// for each lane count per row and keep the fastest (per precision).
+void Solver::tune_lanes(int l) {
+  Level &L = *lev[l];
+  if (L.n < 20000) return;
+  static const int cand[] = {4, 8, 16, 32, 64};
+  hipEvent_t a, b;
+  MG_HIP(hipEventCreate(&a));
+  MG_HIP(hipEventCreate(&b));
+  launch_fill(L.n, 1.0, L.r.p, st);
+  float best = 1e30f, best32 = 1e30f;
+  int pick = L.lanes, pick32 = L.lanes32;
+  const bool do32 = mixed() && L.val32.p;
+  if (do32) launch_d2f(L.n, L.r.p, L.r32.p, nullptr, st);
+  for (int g : cand) {
+    CsrView<double> A = L.view();
+    A.lanes = g;
+    launch_spmv<double>(A, L.r.p, L.t.p, st);   // warm
+    MG_HIP(hipEventRecord(a, st));
+    for (int rep = 0; rep < 3; ++rep) launch_spmv<double>(A, L.r.p, L.t.p, st);
+    MG_HIP(hipEventRecord(b, st));
+    MG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    MG_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms < best) { best = ms; pick = g; }
+    if (do32) {
+      CsrView<float> F = L.view32();
+      F.lanes = g;
+      launch_spmv<float>(F, L.r32.p, L.t32.p, st);
+      MG_HIP(hipEventRecord(a, st));
+      for (int rep = 0; rep < 3; ++rep) launch_spmv<float>(F, L.r32.p, L.t32.p, st);
+      MG_HIP(hipEventRecord(b, st));
+      MG_HIP(hipEventSynchronize(b));
+      MG_HIP(hipEventElapsedTime(&ms, a, b));
+      if (ms < best32) { best32 = ms; pick32 = g; }
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  L.lanes = pick;
+  if (do32) L.lanes32 = pick32;
 }
 
 // omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min), lambda_max by the
@@ -381,8 +427,10 @@ void Solver::smooth(Level &L, const T *r, T *&a, T *&b, int sweeps, bool from_ze
   const T om = (T)L.omega;
   int k = 0;
   if (from_zero) {
-    if (sweeps >= 2) { launch_jacobi_first2<T>(A, dinv, r, om, a, done, st); k = 2; }
-    else if (sweeps == 1) { launch_jacobi_first<T>(L.n, dinv, r, om, a, done, st); k = 1; }
+    // the first sweep from z = 0 is elementwise; fusing it into the second
+    // would gather both r and D^-1 per entry, which costs more than the extra
+    // pass over three vectors
+    if (sweeps >= 1) { launch_jacobi_first<T>(L.n, dinv, r, om, a, done, st); k = 1; }
     else { launch_zero_t<T>(L.n, a, done, st); }
   }
   for (; k < sweeps; ++k) {
@@ -399,7 +447,10 @@ void Solver::vcycle(int l, const T *r, T *z) {
     launch_dense_apply<T>(L.n, Ainv.p, r, z, done, st);
     return;
   }
+  // start in the buffer that makes the last sweep land in z
+  const int swaps = (opt.pre_sweeps > 0 ? opt.pre_sweeps - 1 : 0) + opt.post_sweeps;
   T *a = z, *b = Buf<T>::t(L).p;
+  if (swaps % 2) std::swap(a, b);
   smooth<T>(L, r, a, b, opt.pre_sweeps, true);
   if (l + 1 < nlev) {
     Level &C = *lev[l + 1];

@@ -10,7 +10,8 @@ namespace mgpbd {
 
 struct Level {
   int64_t n = 0, nnz = 0;
-  int lanes = 16;
+  int lanes = 16;    // lanes per row of the FP64 row-group kernels (autotuned)
+  int lanes32 = 16;  // same for the FP32 copy
   double omega = 0.0;
   DevBuf<int64_t> rowptr;
   DevBuf<int32_t> col;
@@ -47,7 +48,7 @@ struct Level {
   }
   CsrView<float> view32() const {
     CsrView<float> v;
-    v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val32.p; v.lanes = lanes;
+    v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val32.p; v.lanes = lanes32;
     return v;
   }
 };
@@ -132,6 +133,7 @@ class Solver {
   void galerkin_symbolic(int l);
   void galerkin_numeric(int l);
   void power_omega(int l);
+  void tune_lanes(int l);
   void factor_last();
   void iterate_once(int k);
   template <class T> void vcycle(int l, const T *r, T *z);
