@@ -77,6 +77,11 @@ typedef struct {
   int32_t use_graph;    /* capture one PCG iteration in a hipGraph and replay it: 1 */
   int32_t profile_spmv; /* time every fine-level A p product with HIP events (the PCG
                            loop then launches kernels directly, without the graph): 0 */
+  int32_t spmv_tile;    /* CSR pass variant: 0 = autotuned on levels with >= 20000 rows
+                           (timed at setup), -1 = lanes-per-row kernels only,
+                           1024 / 2048 / 4096 = LDS stream kernels with that tile: 0 */
+  int32_t spmv_lanes;   /* lanes per row of the lanes-per-row kernels when not autotuned
+                           (4, 8, 16, 32, 64; 0 = from the mean row length): 0 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.

@@ -28,7 +28,8 @@ class Options(C.Structure):
                 ("max_pcg", C.c_int32), ("seed", C.c_uint64), ("reuse_interval", C.c_int32),
                 ("b_mode", C.c_int32), ("eps_b", C.c_double), ("precision", C.c_int32),
                 ("lmax_scale", C.c_double), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32), ("profile_spmv", C.c_int32)]
+                ("use_graph", C.c_int32), ("profile_spmv", C.c_int32),
+                ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32)]
 
 
 class Mesh(C.Structure):

@@ -89,6 +89,12 @@ void check_options(const mgpbd_options &o) {
   MG_REQUIRE(o.precision == MGPBD_PREC_FP64 || o.precision == MGPBD_PREC_MIXED,
              MGPBD_E_INVALID_ARG, "precision");
   MG_REQUIRE(o.reuse_interval >= 0, MGPBD_E_INVALID_ARG, "reuse_interval");
+  MG_REQUIRE(o.spmv_tile == 0 || o.spmv_tile == -1 || o.spmv_tile == 1024 ||
+                 o.spmv_tile == 2048 || o.spmv_tile == 4096,
+             MGPBD_E_INVALID_ARG, "spmv_tile must be 0, -1, 1024, 2048 or 4096");
+  MG_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 4 || o.spmv_lanes == 8 || o.spmv_lanes == 16 ||
+                 o.spmv_lanes == 32 || o.spmv_lanes == 64,
+             MGPBD_E_INVALID_ARG, "spmv_lanes must be 0, 4, 8, 16, 32 or 64");
 }
 
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
@@ -126,6 +132,8 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->check_every = 8;
   o->use_graph = 1;
   o->profile_spmv = 0;
+  o->spmv_tile = 0;
+  o->spmv_lanes = 0;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {

@@ -10,6 +10,7 @@ namespace mgpbd {
 // wavefront; every lane of the group receives the total. Deterministic.
 template <int G, class T>
 __device__ __forceinline__ T group_sum(T v) {
+  static_assert(G >= 1 && G <= 64, "group size");
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;

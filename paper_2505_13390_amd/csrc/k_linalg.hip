@@ -24,41 +24,173 @@ int lanes_for_rowlen(double mean) {
     default: LAUNCH(64); break;      \
   }
 
-// sum over the row [lo, hi) of val[e] * x[col[e]], G lanes, fixed tree
-template <int G, class T>
-__device__ __forceinline__ T row_dot(int64_t lo, int64_t hi, int sub, const int32_t *__restrict__ col,
-                                     const T *__restrict__ val, const T *__restrict__ x) {
-  T s = 0;
-#pragma unroll 4
-  for (int64_t e = lo + sub; e < hi; e += G) s += val[e] * x[col[e]];
-  return group_sum<G>(s);
-}
+// ------------------------------------------------------------ row ops
+// What a CSR pass does with the row sum s = (A x)_i. Every pass of the
+// solving phase (product, smoother sweep, residual, PCG product + dot) is one
+// of these epilogues on one of the two product kernels below.
+template <class T>
+struct OpSpmv {
+  T *y;
+  __device__ void operator()(int64_t i, T s, double &) const { y[i] = s; }
+};
+template <class T>
+struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi)
+  const T *dinv, *r, *zi;
+  T omega;
+  T *zo;
+  __device__ void operator()(int64_t i, T s, double &) const {
+    zo[i] = zi[i] + omega * ((r[i] - s) * dinv[i]);
+  }
+};
+template <class T>
+struct OpResidual {  // res = r - A z
+  const T *r;
+  T *res;
+  __device__ void operator()(int64_t i, T s, double &) const { res[i] = r[i] - s; }
+};
+struct OpPcgDot {  // q = A p, accumulate p^T q
+  const double *p;
+  double *q;
+  __device__ void operator()(int64_t i, double s, double &acc) const {
+    q[i] = s;
+    acc += p[i] * s;
+  }
+};
 
-// ------------------------------------------------------------------ SpMV
-template <int G, class T>
-__global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const int64_t *__restrict__ rp,
+// Row-group kernel: G lanes per row, strided loads, fixed-tree lane sum.
+template <int G, class T, class Op>
+__global__ __launch_bounds__(kBlock) void k_rows(const int *done, int64_t n,
+                                                 const int64_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
-                                                 const T *__restrict__ x, T *__restrict__ y) {
+                                                 const T *__restrict__ x, Op op,
+                                                 double *partials) {
+  if (done && *done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
   int64_t lo, hi;
   block_range(n, lo, hi);
+  double acc = 0.0;
   for (int64_t base = lo; base < hi; base += R) {
     int64_t i = base + grp;
     bool ok = i < hi;
-    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, x);
-    if (ok && sub == 0) y[i] = s;
+    int64_t a = ok ? rp[i] : 0, b = ok ? rp[i + 1] : 0;
+    T s = 0;
+#pragma unroll 4
+    for (int64_t e = a + sub; e < b; e += G) s += val[e] * x[col[e]];
+    s = group_sum<G, T>(s);
+    if (ok && sub == 0) op(i, s, acc);
+  }
+  if (partials) {
+    double v[1] = {acc};
+    block_partials<1>(v, partials);
   }
 }
 
-template <class T>
-void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s) {
-  if (A.n == 0) return;
+// Stream kernel: a block walks a contiguous range of row tiles; for each tile
+// all threads first load the tile's entries with independent coalesced loads
+// (TILE / kBlock per thread) and stage the products in LDS, then 8 lanes per
+// row add the row's segment and apply the epilogue.
+template <int TILE, class T, class Op>
+__global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntiles,
+                                                   const int64_t *__restrict__ tiles,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const T *__restrict__ x, Op op,
+                                                   double *partials) {
+  if (done && *done) return;
+  constexpr int PER = TILE / kBlock;
+  constexpr int LR = 8;                 // lanes per row in the reduction
+  __shared__ T prod[TILE];
+  int64_t t_lo, t_hi;
+  block_range(ntiles, t_lo, t_hi);
+  double acc = 0.0;
+  for (int64_t t = t_lo; t < t_hi; ++t) {
+    const int64_t r0 = tiles[t], r1 = tiles[t + 1];
+    const int64_t e0 = rp[r0], e1 = rp[r1];
+    int32_t c[PER];
+    T v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      int64_t e = e0 + threadIdx.x + (int64_t)j * kBlock;
+      bool in = e < e1;
+      c[j] = in ? col[e] : 0;
+      v[j] = in ? val[e] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) prod[threadIdx.x + j * kBlock] = v[j] * x[c[j]];
+    __syncthreads();
+    const int sub = threadIdx.x % LR;
+    for (int64_t base = r0; base < r1; base += kBlock / LR) {
+      int64_t i = base + threadIdx.x / LR;
+      bool ok = i < r1;
+      T s = 0;
+      if (ok) {
+        int a = (int)(rp[i] - e0), b = (int)(rp[i + 1] - e0);
+        for (int k = a + sub; k < b; k += LR) s += prod[k];
+      }
+      s = group_sum<LR, T>(s);
+      if (ok && sub == 0) op(i, s, acc);
+    }
+    __syncthreads();
+  }
+  if (partials) {
+    double vv[1] = {acc};
+    block_partials<1>(vv, partials);
+  }
+}
+
+#define MG_DISPATCH_TILE(tile, LAUNCH) \
+  switch (tile) {                      \
+    case 1024: LAUNCH(1024); break;    \
+    case 4096: LAUNCH(4096); break;    \
+    default: LAUNCH(2048); break;      \
+  }
+
+template <class T, class Op>
+static int launch_pass(const CsrView<T> &A, const T *x, Op op, const int *done, double *partials,
+                       hipStream_t s) {
+  if (A.n == 0) return 0;
+  if (A.tile > 0) {
+    int grid = grid_for(A.ntiles, 1);
+#define L_(TL) k_stream<TL, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
+    MG_DISPATCH_TILE(A.tile, L_);
+#undef L_
+    return grid;
+  }
   int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_spmv<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y)
+#define L_(G) k_rows<G, T, Op><<<grid, kBlock, 0, s>>>(done, A.n, A.rowptr, A.col, A.val, x, op, partials)
   MG_DISPATCH_G(A.lanes, L_);
 #undef L_
+  return grid;
+}
+
+bool build_row_tiles(const std::vector<int64_t> &rp, int tile, std::vector<int64_t> &tiles) {
+  tiles.clear();
+  const int64_t n = (int64_t)rp.size() - 1;
+  int64_t r = 0;
+  tiles.push_back(0);
+  while (r < n) {
+    int64_t start = rp[r];
+    if (rp[r + 1] - start > tile) return false;
+    int64_t q = r + 1;
+    while (q < n && rp[q + 1] - start <= tile) ++q;
+    tiles.push_back(q);
+    r = q;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ SpMV
+template <class T>
+void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s) {
+  launch_pass<T>(A, x, OpSpmv<T>{y}, nullptr, nullptr, s);
+}
+
+int launch_spmv_dot_partials(const CsrView<double> &A, const double *p, double *q,
+                             const int *done, double *partials, hipStream_t s) {
+  return launch_pass<double>(A, p, OpPcgDot{p, q}, done, partials, s);
 }
 
 // ------------------------------------------------------------ smoother
@@ -72,78 +204,6 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_first(int64_t n, const T *__r
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) z[i] = omega * (r[i] * dinv[i]);
 }
 
-template <int G, class T>
-__global__ __launch_bounds__(kBlock) void k_jacobi_first2(int64_t n, const int64_t *__restrict__ rp,
-                                                          const int32_t *__restrict__ col,
-                                                          const T *__restrict__ val,
-                                                          const T *__restrict__ dinv,
-                                                          const T *__restrict__ r, T omega,
-                                                          T *__restrict__ z, const int *done) {
-  if (done && *done) return;
-  constexpr int R = kBlock / G;
-  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  for (int64_t base = lo; base < hi; base += R) {
-    int64_t i = base + grp;
-    bool ok = i < hi;
-    int64_t a = ok ? rp[i] : 0, b = ok ? rp[i + 1] : 0;
-    T s = 0;
-#pragma unroll 4
-    for (int64_t e = a + sub; e < b; e += G) {
-      int32_t j = col[e];
-      s += val[e] * (omega * (r[j] * dinv[j]));
-    }
-    s = group_sum<G>(s);
-    if (ok && sub == 0) {
-      T ri = r[i], di = dinv[i];
-      T z1 = omega * (ri * di);
-      z[i] = z1 + omega * ((ri - s) * di);
-    }
-  }
-}
-
-template <int G, class T>
-__global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, const int64_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ col,
-                                                   const T *__restrict__ val,
-                                                   const T *__restrict__ dinv,
-                                                   const T *__restrict__ r, T omega,
-                                                   const T *__restrict__ zi, T *__restrict__ zo,
-                                                   const int *done) {
-  if (done && *done) return;
-  constexpr int R = kBlock / G;
-  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  for (int64_t base = lo; base < hi; base += R) {
-    int64_t i = base + grp;
-    bool ok = i < hi;
-    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, zi);
-    if (ok && sub == 0) zo[i] = zi[i] + omega * ((r[i] - s) * dinv[i]);
-  }
-}
-
-template <int G, class T>
-__global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const int64_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ col,
-                                                     const T *__restrict__ val,
-                                                     const T *__restrict__ r,
-                                                     const T *__restrict__ z,
-                                                     T *__restrict__ res, const int *done) {
-  if (done && *done) return;
-  constexpr int R = kBlock / G;
-  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  for (int64_t base = lo; base < hi; base += R) {
-    int64_t i = base + grp;
-    bool ok = i < hi;
-    T s = row_dot<G, T>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, z);
-    if (ok && sub == 0) res[i] = r[i] - s;
-  }
-}
-
 template <class T>
 void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z, const int *done,
                          hipStream_t s) {
@@ -151,33 +211,14 @@ void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z, co
   k_jacobi_first<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dinv, r, omega, z, done);
 }
 template <class T>
-void launch_jacobi_first2(const CsrView<T> &A, const T *dinv, const T *r, T omega, T *z,
-                          const int *done, hipStream_t s) {
-  if (A.n == 0) return;
-  int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) \
-  k_jacobi_first2<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, dinv, r, omega, z, done)
-  MG_DISPATCH_G(A.lanes, L_);
-#undef L_
-}
-template <class T>
 void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega, const T *zi, T *zo,
                    const int *done, hipStream_t s) {
-  if (A.n == 0) return;
-  int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) \
-  k_jacobi<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, dinv, r, omega, zi, zo, done)
-  MG_DISPATCH_G(A.lanes, L_);
-#undef L_
+  launch_pass<T>(A, zi, OpJacobi<T>{dinv, r, zi, omega, zo}, done, nullptr, s);
 }
 template <class T>
 void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
                      hipStream_t s) {
-  if (A.n == 0) return;
-  int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_residual<G, T><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, A.val, r, z, res, done)
-  MG_DISPATCH_G(A.lanes, L_);
-#undef L_
+  launch_pass<T>(A, z, OpResidual<T>{r, res}, done, nullptr, s);
 }
 
 // ------------------------------------------------------------ transfers
@@ -399,31 +440,6 @@ void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z,
   k_fin_init_p<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv_dot(const PcgCtl *ctl, int64_t n,
-                                                         const int64_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ col,
-                                                         const double *__restrict__ val,
-                                                         const double *__restrict__ p,
-                                                         double *__restrict__ q,
-                                                         double *partials) {
-  if (ctl->done) return;
-  constexpr int R = kBlock / G;
-  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t base = lo; base < hi; base += R) {
-    int64_t i = base + grp;
-    bool ok = i < hi;
-    double s = row_dot<G, double>(ok ? rp[i] : 0, ok ? rp[i + 1] : 0, sub, col, val, p);
-    if (ok && sub == 0) {
-      q[i] = s;
-      v[0] += p[i] * s;
-    }
-  }
-  block_partials<1>(v, partials);
-}
 __global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *partials,
                                                    int nparts) {
   if (ctl->done) return;
@@ -437,10 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *pa
 }
 void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
                          RedBuf rb, hipStream_t s) {
-  int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_pcg_spmv_dot<G><<<grid, kBlock, 0, s>>>(ctl, A.n, A.rowptr, A.col, A.val, p, q, rb.partials)
-  MG_DISPATCH_G(A.lanes, L_);
-#undef L_
+  const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field
+  int grid = launch_spmv_dot_partials(A, p, q, done, rb.partials, s);
   k_fin_pq<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
 }
 
@@ -672,8 +686,6 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
   template void launch_spmv<T>(const CsrView<T> &, const T *, T *, hipStream_t);                    \
   template void launch_jacobi_first<T>(int64_t, const T *, const T *, T, T *, const int *,          \
                                        hipStream_t);                                                \
-  template void launch_jacobi_first2<T>(const CsrView<T> &, const T *, const T *, T, T *,           \
-                                        const int *, hipStream_t);                                  \
   template void launch_jacobi<T>(const CsrView<T> &, const T *, const T *, T, const T *, T *,       \
                                  const int *, hipStream_t);                                         \
   template void launch_residual<T>(const CsrView<T> &, const T *, const T *, T *, const int *,      \

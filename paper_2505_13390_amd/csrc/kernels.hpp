@@ -11,6 +11,10 @@ namespace mgpbd {
 int lanes_for_rowlen(double mean_nnz_per_row);
 
 // CSR view of one level (device pointers).
+// CSR view of one level (device pointers) and the product variant chosen
+// for it: tile == 0 -> row-group kernels with `lanes` lanes per row;
+// tile > 0 -> LDS-staged stream kernels over row tiles of at most `tile`
+// entries (tiles[0..ntiles] are the first rows of the tiles).
 template <class T>
 struct CsrView {
   int64_t n = 0, nnz = 0;
@@ -18,16 +22,23 @@ struct CsrView {
   const int32_t *col = nullptr;
   const T *val = nullptr;
   int lanes = 16;
+  int tile = 0;
+  int64_t ntiles = 0;
+  const int64_t *tiles = nullptr;
 };
+
+// Row tiles of at most `tile` entries (host, from the row pointers); returns
+// false when some row alone is longer than a tile.
+bool build_row_tiles(const std::vector<int64_t> &rowptr, int tile, std::vector<int64_t> &tiles);
 
 // ---------------- sparse kernels of the V-cycle (T = double or float) ----
 template <class T> void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s);
+// q = A p and the partial sums of p^T q (one per block of `grid`); returns grid
+int launch_spmv_dot_partials(const CsrView<double> &A, const double *p, double *q,
+                             const int *done, double *partials, hipStream_t s);
 // z = omega D^-1 r (first sweep from z = 0)
 template <class T> void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z,
                                             const int *done, hipStream_t s);
-// z = z1 + omega D^-1 (r - A z1) with z1 = omega D^-1 r formed on the fly
-template <class T> void launch_jacobi_first2(const CsrView<T> &A, const T *dinv, const T *r,
-                                             T omega, T *z, const int *done, hipStream_t s);
 // zo = zi + omega D^-1 (r - A zi)
 template <class T> void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega,
                                       const T *zi, T *zo, const int *done, hipStream_t s);

@@ -99,47 +99,89 @@ void Solver::finish_level(int l) {
   power_omega(l);
 }
 
-// Autotuner of the row-group CSR kernels: on large levels, time one product
-// for each lane count per row and keep the fastest (per precision).
+// Autotuner of the CSR passes: on large levels, time one product for each
+// variant (lanes per row of the row-group kernel; tile size of the LDS stream
+// kernel) and keep the fastest, separately for FP64 and FP32 values.
 void Solver::tune_lanes(int l) {
   Level &L = *lev[l];
-  if (L.n < 20000) return;
-  static const int cand[] = {4, 8, 16, 32, 64};
+  L.tile = L.tile32 = 0;
+  if (opt.spmv_lanes > 0) L.lanes = L.lanes32 = opt.spmv_lanes;
+  if (opt.spmv_tile > 0 && L.n > 0) {
+    std::vector<int64_t> hrp(L.n + 1), part;
+    L.rowptr.download(hrp.data(), L.n + 1, st);
+    MG_HIP(hipStreamSynchronize(st));
+    if (build_row_tiles(hrp, opt.spmv_tile, part)) {
+      L.tile = L.tile32 = opt.spmv_tile;
+      L.tiles.upload(part.data(), part.size(), st);
+      L.tiles32.upload(part.data(), part.size(), st);
+      L.ntiles = L.ntiles32 = (int64_t)part.size() - 1;
+      MG_HIP(hipStreamSynchronize(st));
+    }
+    return;
+  }
+  if (opt.spmv_tile < 0 || opt.spmv_lanes > 0 || L.n < 20000) return;
+  std::vector<int64_t> hrp(L.n + 1);
+  L.rowptr.download(hrp.data(), L.n + 1, st);
+  MG_HIP(hipStreamSynchronize(st));
+  struct Cand { int lanes, tile; std::vector<int64_t> part; };
+  std::vector<Cand> cands;
+  for (int g : {8, 16, 32, 64}) cands.push_back({g, 0, {}});
+  for (int t : {1024, 2048, 4096}) {
+    Cand c{16, t, {}};
+    if (build_row_tiles(hrp, t, c.part)) cands.push_back(std::move(c));
+  }
   hipEvent_t a, b;
   MG_HIP(hipEventCreate(&a));
   MG_HIP(hipEventCreate(&b));
   launch_fill(L.n, 1.0, L.r.p, st);
-  float best = 1e30f, best32 = 1e30f;
-  int pick = L.lanes, pick32 = L.lanes32;
   const bool do32 = mixed() && L.val32.p;
   if (do32) launch_d2f(L.n, L.r.p, L.r32.p, nullptr, st);
-  for (int g : cand) {
-    CsrView<double> A = L.view();
-    A.lanes = g;
-    launch_spmv<double>(A, L.r.p, L.t.p, st);   // warm
+  DevBuf<int64_t> tmp;
+  float best = 1e30f, best32 = 1e30f;
+  size_t pick = 0, pick32 = 0;
+  auto timeit = [&](auto &&fn) {
+    fn();  // warm
     MG_HIP(hipEventRecord(a, st));
-    for (int rep = 0; rep < 3; ++rep) launch_spmv<double>(A, L.r.p, L.t.p, st);
+    for (int rep = 0; rep < 3; ++rep) fn();
     MG_HIP(hipEventRecord(b, st));
     MG_HIP(hipEventSynchronize(b));
     float ms = 0.f;
     MG_HIP(hipEventElapsedTime(&ms, a, b));
-    if (ms < best) { best = ms; pick = g; }
+    return ms;
+  };
+  for (size_t k = 0; k < cands.size(); ++k) {
+    Cand &c = cands[k];
+    if (c.tile) tmp.upload(c.part.data(), c.part.size(), st);
+    CsrView<double> A = L.view();
+    A.lanes = c.lanes; A.tile = c.tile;
+    A.ntiles = c.tile ? (int64_t)c.part.size() - 1 : 0;
+    A.tiles = c.tile ? tmp.p : nullptr;
+    float ms = timeit([&] { launch_spmv<double>(A, L.r.p, L.t.p, st); });
+    if (ms < best) { best = ms; pick = k; }
     if (do32) {
       CsrView<float> F = L.view32();
-      F.lanes = g;
-      launch_spmv<float>(F, L.r32.p, L.t32.p, st);
-      MG_HIP(hipEventRecord(a, st));
-      for (int rep = 0; rep < 3; ++rep) launch_spmv<float>(F, L.r32.p, L.t32.p, st);
-      MG_HIP(hipEventRecord(b, st));
-      MG_HIP(hipEventSynchronize(b));
-      MG_HIP(hipEventElapsedTime(&ms, a, b));
-      if (ms < best32) { best32 = ms; pick32 = g; }
+      F.lanes = c.lanes; F.tile = c.tile; F.ntiles = A.ntiles; F.tiles = A.tiles;
+      float ms32 = timeit([&] { launch_spmv<float>(F, L.r32.p, L.t32.p, st); });
+      if (ms32 < best32) { best32 = ms32; pick32 = k; }
     }
   }
+  MG_HIP(hipStreamSynchronize(st));
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  L.lanes = pick;
-  if (do32) L.lanes32 = pick32;
+  const Cand &c = cands[pick];
+  L.lanes = c.lanes;
+  L.tile = c.tile;
+  if (c.tile) { L.tiles.upload(c.part.data(), c.part.size(), st); L.ntiles = (int64_t)c.part.size() - 1; }
+  if (do32) {
+    const Cand &c32 = cands[pick32];
+    L.lanes32 = c32.lanes;
+    L.tile32 = c32.tile;
+    if (c32.tile) {
+      L.tiles32.upload(c32.part.data(), c32.part.size(), st);
+      L.ntiles32 = (int64_t)c32.part.size() - 1;
+    }
+  }
+  MG_HIP(hipStreamSynchronize(st));
 }
 
 // omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min), lambda_max by the

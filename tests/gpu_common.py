@@ -22,7 +22,7 @@ def opts(**kw):
     """Matching (oracle, gpu) options; gpu-only keys: precision, use_graph,
     check_every, profile_spmv."""
     gkw = {k: kw.pop(k) for k in list(kw) if k in ("precision", "use_graph", "check_every",
-                                                   "profile_spmv")}
+                                                   "profile_spmv", "spmv_tile", "spmv_lanes")}
     o = O.default_opts(**kw)
     if gkw.get("precision", 0) == B.PREC_MIXED:
         o.flexible = 1

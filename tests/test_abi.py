@@ -45,6 +45,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.omega_relax == 0.1 and o.tol == 1e-6 and o.seed == 20250513
     assert o.reuse_interval == 20 and o.precision == 0 and o.lmax_scale == 1.05
     assert o.use_graph == 1 and o.check_every == 8 and o.profile_spmv == 0
+    assert o.spmv_tile == 0 and o.spmv_lanes == 0
 
 
 def test_null_arguments_rejected_without_device_work():

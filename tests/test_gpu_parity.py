@@ -157,6 +157,19 @@ def test_c0_frame_with_forced_pcg_counts():
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("tile,lanes", [(1024, 0), (2048, 0), (4096, 0), (-1, 4), (-1, 64)])
+def test_csr_pass_variants_match_oracle(tile, lanes):
+    """Every CSR product variant the autotuner may pick (LDS stream tiles and
+    lanes-per-row counts) gives oracle parity on the 8x8x32 beam."""
+    w = W.beam_c0()
+    sim, body, pos, vel, ores, gres = run_both(w, 3, spmv_tile=tile, spmv_lanes=lanes)
+    compare_hierarchy(sim, body, "tile %d lanes %d" % (tile, lanes), exact=False)
+    err = rel_pos_err(body.positions(), pos)
+    log("  position error %.3e iters %s %s" % (err, ores[0]["pcg_iters"].tolist(),
+                                              gres[0]["pcg_iters"].tolist()))
+    assert err <= 1e-9
+
+
 def test_graph_and_direct_launch_are_bitwise_identical():
     w = W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8)
     res = []
