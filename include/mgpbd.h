@@ -63,7 +63,7 @@ typedef struct {
   int32_t power_iters;  /* power-method iterations for lambda_max (Sec. 4.5): 30 */
   double omega_relax;   /* relaxation of x += omega dx (Algorithm 1 and Sec. 4): 0.1 */
   double tol;           /* PCG stop: |r| <= tol |b| (recurrence residual): 1e-6 */
-  int32_t max_pcg;      /* PCG iteration cap per solve: 1000 */
+  int32_t max_pcg;      /* PCG iteration cap per solve: 5000 */
   uint64_t seed;        /* seed of the solver's own random streams: 20250513 */
   int32_t reuse_interval; /* setup at iteration 0 of frames f with f % R == 0 (Sec. 4.2);
                              0 = setup every iteration (the no-reuse baseline): 20 */

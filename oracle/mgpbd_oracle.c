@@ -70,7 +70,7 @@ typedef struct orc_opts {
   int power_iters;     /* power-method iterations for lambda_max: 30 */
   double omega_relax;  /* x += omega dx (Algorithm 1): 0.1 */
   double tol;          /* PCG relative residual: 1e-6 */
-  int max_pcg;         /* PCG iteration cap: 1000 */
+  int max_pcg;         /* PCG iteration cap: 5000 */
   uint64_t seed;       /* solver's own random streams */
   int reuse_interval;  /* setup at iteration 0 of frames f % R == 0; 0 = every iteration */
   int b_mode;          /* 0 = smoothed near-kernel, 1 = all-ones candidate */
@@ -91,7 +91,7 @@ void orc_default_opts(orc_opts *o) {
   o->power_iters = 30;
   o->omega_relax = 0.1;
   o->tol = 1e-6;
-  o->max_pcg = 1000;
+  o->max_pcg = 5000;
   o->seed = 20250513ULL;
   o->reuse_interval = 20;
   o->b_mode = 0;

@@ -122,7 +122,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->power_iters = 30;
   o->omega_relax = 0.1;
   o->tol = 1e-6;
-  o->max_pcg = 1000;
+  o->max_pcg = 5000;
   o->seed = 20250513ULL;
   o->reuse_interval = 20;
   o->b_mode = 0;

@@ -91,7 +91,13 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int *done, int64_t n,
 // all threads first load the tile's entries with independent coalesced loads
 // (TILE / kBlock per thread) and stage the products in LDS, then 8 lanes per
 // row add the row's segment and apply the epilogue.
-template <int TILE, class T, class Op>
+template <bool NT, class V>
+__device__ __forceinline__ V stream_load(const V *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <int TILE, bool NT, class T, class Op>
 __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntiles,
                                                    const int64_t *__restrict__ tiles,
                                                    const int64_t *__restrict__ rp,
@@ -115,8 +121,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntil
     for (int j = 0; j < PER; ++j) {
       int64_t e = e0 + threadIdx.x + (int64_t)j * kBlock;
       bool in = e < e1;
-      c[j] = in ? col[e] : 0;
-      v[j] = in ? val[e] : (T)0;
+      // matrix entries are read once per pass: non-temporal loads keep the
+      // L2 for the gathered vector
+      c[j] = in ? stream_load<NT>(col + e) : 0;
+      v[j] = in ? stream_load<NT>(val + e) : (T)0;
     }
 #pragma unroll
     for (int j = 0; j < PER; ++j) prod[threadIdx.x + j * kBlock] = v[j] * x[c[j]];
@@ -154,9 +162,15 @@ static int launch_pass(const CsrView<T> &A, const T *x, Op op, const int *done, 
   if (A.n == 0) return 0;
   if (A.tile > 0) {
     int grid = grid_for(A.ntiles, 1);
-#define L_(TL) k_stream<TL, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
-    MG_DISPATCH_TILE(A.tile, L_);
+    if (A.nt) {
+#define L_(TL) k_stream<TL, true, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
+      MG_DISPATCH_TILE(A.tile, L_);
 #undef L_
+    } else {
+#define L_(TL) k_stream<TL, false, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
+      MG_DISPATCH_TILE(A.tile, L_);
+#undef L_
+    }
     return grid;
   }
   int grid = grid_for(A.n * A.lanes, kBlock);

@@ -23,6 +23,7 @@ struct CsrView {
   const T *val = nullptr;
   int lanes = 16;
   int tile = 0;
+  bool nt = false;   // non-temporal loads of the matrix entries (stream kernels)
   int64_t ntiles = 0;
   const int64_t *tiles = nullptr;
 };

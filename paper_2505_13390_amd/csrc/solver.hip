@@ -123,13 +123,14 @@ void Solver::tune_lanes(int l) {
   std::vector<int64_t> hrp(L.n + 1);
   L.rowptr.download(hrp.data(), L.n + 1, st);
   MG_HIP(hipStreamSynchronize(st));
-  struct Cand { int lanes, tile; std::vector<int64_t> part; };
+  struct Cand { int lanes, tile; bool nt; std::vector<int64_t> part; };
   std::vector<Cand> cands;
-  for (int g : {8, 16, 32, 64}) cands.push_back({g, 0, {}});
-  for (int t : {1024, 2048, 4096}) {
-    Cand c{16, t, {}};
-    if (build_row_tiles(hrp, t, c.part)) cands.push_back(std::move(c));
-  }
+  for (int g : {8, 16, 32, 64}) cands.push_back({g, 0, false, {}});
+  for (int t : {1024, 2048, 4096})
+    for (bool ntl : {false, true}) {
+      Cand c{16, t, ntl, {}};
+      if (build_row_tiles(hrp, t, c.part)) cands.push_back(std::move(c));
+    }
   hipEvent_t a, b;
   MG_HIP(hipEventCreate(&a));
   MG_HIP(hipEventCreate(&b));
@@ -153,14 +154,14 @@ void Solver::tune_lanes(int l) {
     Cand &c = cands[k];
     if (c.tile) tmp.upload(c.part.data(), c.part.size(), st);
     CsrView<double> A = L.view();
-    A.lanes = c.lanes; A.tile = c.tile;
+    A.lanes = c.lanes; A.tile = c.tile; A.nt = c.nt;
     A.ntiles = c.tile ? (int64_t)c.part.size() - 1 : 0;
     A.tiles = c.tile ? tmp.p : nullptr;
     float ms = timeit([&] { launch_spmv<double>(A, L.r.p, L.t.p, st); });
     if (ms < best) { best = ms; pick = k; }
     if (do32) {
       CsrView<float> F = L.view32();
-      F.lanes = c.lanes; F.tile = c.tile; F.ntiles = A.ntiles; F.tiles = A.tiles;
+      F.lanes = c.lanes; F.tile = c.tile; F.nt = c.nt; F.ntiles = A.ntiles; F.tiles = A.tiles;
       float ms32 = timeit([&] { launch_spmv<float>(F, L.r32.p, L.t32.p, st); });
       if (ms32 < best32) { best32 = ms32; pick32 = k; }
     }
@@ -171,11 +172,13 @@ void Solver::tune_lanes(int l) {
   const Cand &c = cands[pick];
   L.lanes = c.lanes;
   L.tile = c.tile;
+  L.nt = c.nt;
   if (c.tile) { L.tiles.upload(c.part.data(), c.part.size(), st); L.ntiles = (int64_t)c.part.size() - 1; }
   if (do32) {
     const Cand &c32 = cands[pick32];
     L.lanes32 = c32.lanes;
     L.tile32 = c32.tile;
+    L.nt32 = c32.nt;
     if (c32.tile) {
       L.tiles32.upload(c32.part.data(), c32.part.size(), st);
       L.ntiles32 = (int64_t)c32.part.size() - 1;

@@ -13,6 +13,7 @@ struct Level {
   int lanes = 16;    // lanes per row of the FP64 row-group kernels (autotuned)
   int lanes32 = 16;  // same for the FP32 copy
   int tile = 0, tile32 = 0;  // > 0: LDS stream kernels with row tiles of this many entries
+  bool nt = false, nt32 = false;  // non-temporal matrix loads in the stream kernels
   DevBuf<int64_t> tiles, tiles32;
   int64_t ntiles = 0, ntiles32 = 0;
   double omega = 0.0;
@@ -47,13 +48,13 @@ struct Level {
   CsrView<double> view() const {
     CsrView<double> v;
     v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val.p; v.lanes = lanes;
-    v.tile = tile; v.ntiles = ntiles; v.tiles = tiles.p;
+    v.tile = tile; v.nt = nt; v.ntiles = ntiles; v.tiles = tiles.p;
     return v;
   }
   CsrView<float> view32() const {
     CsrView<float> v;
     v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val32.p; v.lanes = lanes32;
-    v.tile = tile32; v.ntiles = ntiles32; v.tiles = tiles32.p;
+    v.tile = tile32; v.nt = nt32; v.ntiles = ntiles32; v.tiles = tiles32.p;
     return v;
   }
 };
