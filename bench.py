@@ -33,6 +33,17 @@ def spmv_bytes(m: int, nnz: int) -> int:
     return 12 * nnz + 8 * (m + 1) + 8 * m + 8 * m
 
 
+def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int) -> int:
+    """Algorithmic bytes of one matrix-free fine-level A p product: the vertex
+    gather reads the incidence pointers, rows and gradients, the inverse
+    masses and p, and writes u (4 doubles per vertex); the row pass reads the
+    row vertex ids, the gradient planes (3 doubles per edge row, 9 per volume
+    row), alpha~, p and u, and writes q."""
+    gather = 8 * (nv + 1) + 4 * n_inc + 24 * n_inc + 8 * nv + 8 * m + 32 * nv
+    rows = 16 * m + 24 * n_edges + 72 * n_vols + 8 * m + 8 * m + 32 * nv + 8 * m
+    return gather + rows
+
+
 def cpu_baseline(w, seconds_hint: float = 20.0):
     """The FP64 oracle on the same workload: frame 0, global iteration 0,
     a fixed number of preconditioned CG iterations (setup not timed)."""
@@ -70,6 +81,8 @@ def main():
     ap.add_argument("--reuse", type=int, default=20)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--max-pcg", type=int, default=None)
+    ap.add_argument("--fine", default="mf", choices=["mf", "csr"],
+                    help="fine-level products: matrix-free (default) or assembled CSR")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -93,7 +106,8 @@ def main():
     n_iters = args.iters or w.iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
-                                  profile_spmv=0 if args.no_profile else 1)
+                                  profile_spmv=0 if args.no_profile else 1,
+                                  matrix_free=1 if args.fine == "mf" else 0)
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
     t0 = time.perf_counter()
@@ -124,11 +138,18 @@ def main():
     roof = None
     if spmv_calls:
         avg_ms = spmv_ms / spmv_calls
-        nbytes = spmv_bytes(body.m, body.nnz)
+        if args.fine == "mf":
+            ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
+            nbytes = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol, ne, nvol)
+            kname = ("k_mf_gather + k_mf_rows<OpPcgDot> (matrix-free fine-level A p with "
+                     "p^T A p)")
+        else:
+            nbytes = spmv_bytes(body.m, body.nnz)
+            kname = "k_rows/k_stream<OpPcgDot> (CSR fine-level A p with p^T A p)"
         ach = nbytes / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "k_pcg_spmv_dot (fine-level A p with p^T A p)",
+                "kernel": kname,
                 "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
                 "launches": int(spmv_calls)}
     out = {
@@ -139,6 +160,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "rows": body.m, "nnz": body.nnz,
                    "iters_per_frame": n_iters, "precision": args.precision,
+                   "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
                    "reuse_interval": args.reuse, "tol": 1e-6,
                    "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,

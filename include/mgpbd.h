@@ -82,6 +82,12 @@ typedef struct {
                            1024 / 2048 / 4096 = LDS stream kernels with that tile: 0 */
   int32_t spmv_lanes;   /* lanes per row of the lanes-per-row kernels when not autotuned
                            (4, 8, 16, 32, 64; 0 = from the mean row length): 0 */
+  int32_t matrix_free;  /* 1: the fine-level products of PCG and of the V-cycle (A p,
+                           smoother sweeps, residual) apply J W J^T + alpha~ from the
+                           constraint gradients instead of the assembled values (the
+                           assembled A still feeds the setup, the Galerkin products and
+                           the Jacobi diagonal); 0: assembled CSR. Simulation contexts
+                           only; mgpbd_solve always uses the caller's CSR: 1 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.
@@ -160,8 +166,8 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
 /* Create a context with no body, for mgpbd_solve only. */
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out);
 
-/* Set the lazy-setup policy (Sec. 4.2, Algorithm 1 line "setup AMG for every
-   few frames"): max_levels caps the hierarchy depth (1..32), reuse_interval R
+/* Set the lazy-setup policy (Sec. 4.2; Algorithm 1 rebuilds the hierarchy
+   only every few frames): max_levels caps the hierarchy depth (1..32), reuse_interval R
    runs the setup at iteration 0 of frames f with f % R == 0, R = 0 at every
    iteration. Marks the hierarchy stale so the next step rebuilds it. */
 mgpbd_status mgpbd_setup(mgpbd_ctx *ctx, int32_t max_levels, int32_t reuse_interval);
@@ -222,15 +228,29 @@ mgpbd_status mgpbd_selftest_sqrt_div(int64_t n, const double *a, const double *b
                                      double *q);
 
 /* ---- batching: many bodies advanced together (block-diagonal system) ---- */
-/* Group n already created contexts (borrowed; they must outlive the batch and
-   share precision). Their rows are concatenated into one block-diagonal A so
-   that every kernel of a global iteration covers all bodies in one launch;
-   each body keeps its own PCG scalars and convergence test. */
+/* Group n already created single-body contexts (borrowed; they must outlive
+   the batch). They must share dt, gravity and precision; the batch takes the
+   other options from ctxs[0]. Their rows are concatenated into one
+   block-diagonal A so that every kernel of a global iteration covers all
+   bodies in one launch; each body keeps its own hierarchy depth, Jacobi
+   weights, coarsest factor, PCG scalars and convergence test, so each body's
+   result is the one its own context would compute (up to the rounding order
+   of reductions). Errors: E_INVALID_ARG for mismatched contexts or a batch
+   with 2^31 or more entries of A. */
 mgpbd_status mgpbd_batch_create(mgpbd_ctx *const *ctxs, int32_t n, mgpbd_batch **out);
 /* One frame for every body: xyz[3*k+0..2] and vxyz[3*k+0..2] are body k's
-   device SoA arrays. st may be NULL or an array of n stats structs. */
+   device SoA arrays (updated in place). st may be NULL or an array of n
+   stats structs (times are those of the whole batch). Iteration counts set
+   with mgpbd_force_pcg_iters on a member context apply to that body. A body
+   whose |b| falls below eps_b stops iterating (zero right-hand side
+   afterwards). The lazy-setup schedule follows the batch's own frame count;
+   mgpbd_setup on the batch context changes it. */
 mgpbd_status mgpbd_batch_step(mgpbd_batch *b, double *const *xyz, double *const *vxyz,
                               int32_t n_iters, mgpbd_step_stats *st);
+/* The batch's system context, for mgpbd_setup, mgpbd_set_stream and the
+   inspection calls (levels hold all bodies' rows back to back). Owned by the
+   batch: mgpbd_destroy ignores it. */
+mgpbd_ctx *mgpbd_batch_context(mgpbd_batch *b);
 void mgpbd_batch_destroy(mgpbd_batch *b);
 
 #ifdef __cplusplus

@@ -380,7 +380,7 @@ void orc_sim_pattern(const orc_sim *s, int64_t *rowptr, int32_t *col) {
   memcpy(col, s->A.col, sizeof(int32_t) * s->A.nnz);
 }
 
-/* C and grad C for all rows (Algorithm 1, "calculate C and grad C") */
+/* C and grad C for all rows (Algorithm 1: constraint values and gradients) */
 void orc_sim_constraints(orc_sim *s, const double *pos, double *C, double *grad) {
   for (int64_t r = 0; r < s->m; ++r) {
     double g[12];
@@ -1096,7 +1096,7 @@ int orc_sim_step(orc_sim *s, double *pos, double *vel, int n_iters, double *bnor
   double *xold = malloc(sizeof(double) * 3 * N);
   double *b = malloc(sizeof(double) * (m ? m : 1));
   double *dl = malloc(sizeof(double) * (m ? m : 1));
-  /* semi-implicit Euler predict (Algorithm 1, first line) */
+  /* semi-implicit Euler predict (Algorithm 1, Eq. 1) */
   for (int64_t v = 0; v < N; ++v)
     for (int k = 0; k < 3; ++k) {
       xold[3 * v + k] = pos[3 * v + k];
@@ -1150,7 +1150,7 @@ int orc_sim_step(orc_sim *s, double *pos, double *vel, int n_iters, double *bnor
     for (int64_t r = 0; r < m; ++r) s->lambda[r] = s->lambda[r] + dl[r];
     if (bn < s->o.eps_b) break;
   }
-  /* v = (x - x_old) / dt (Algorithm 1, last line) */
+  /* v = (x - x_old) / dt, the velocity update that ends Algorithm 1 */
   for (int64_t v = 0; v < N; ++v)
     for (int k = 0; k < 3; ++k) vel[3 * v + k] = (pos[3 * v + k] - xold[3 * v + k]) / dt;
   s->frame++;

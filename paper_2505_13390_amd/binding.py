@@ -29,7 +29,8 @@ class Options(C.Structure):
                 ("b_mode", C.c_int32), ("eps_b", C.c_double), ("precision", C.c_int32),
                 ("lmax_scale", C.c_double), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("profile_spmv", C.c_int32),
-                ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32)]
+                ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32),
+                ("matrix_free", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -94,6 +95,7 @@ _SIGS = {
     "mgpbd_selftest_sqrt_div": (C.c_int, [C.c_int64] + [C.c_void_p] * 4),
     "mgpbd_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "mgpbd_batch_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mgpbd_batch_context": (C.c_void_p, [C.c_void_p]),
     "mgpbd_batch_destroy": (None, [C.c_void_p]),
 }
 
@@ -331,22 +333,46 @@ def mgpbd_batch_create(ctxs):
     h = C.c_void_p()
     st = lib().mgpbd_batch_create(arr, len(ctxs), C.byref(h))
     if st != OK:
-        raise MgpbdError(st, "mgpbd_batch_create")
+        msg = lib().mgpbd_last_error(arr[0]) if len(ctxs) and arr[0] else b""
+        raise MgpbdError(st, "mgpbd_batch_create: " + (msg or b"").decode())
     return h
 
 
-def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters):
+def mgpbd_batch_context(batch):
+    return C.c_void_p(lib().mgpbd_batch_context(batch))
+
+
+def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
+    """One frame for every body of the batch; returns one stats dict per body."""
     import torch
-    xs = (C.c_void_p * (3 * len(xyz_list)))()
-    vs = (C.c_void_p * (3 * len(vxyz_list)))()
+    nb = len(xyz_list)
+    xs = (C.c_void_p * (3 * nb))()
+    vs = (C.c_void_p * (3 * nb))()
     for k, (p, v) in enumerate(zip(xyz_list, vxyz_list)):
         for d in range(3):
             xs[3 * k + d] = _dev(p[d], torch.float64).value
             vs[3 * k + d] = _dev(v[d], torch.float64).value
-    torch.cuda.synchronize()
-    st = lib().mgpbd_batch_step(batch, xs, vs, int(n_iters), None)
-    if st != OK:
-        raise MgpbdError(st, "mgpbd_batch_step")
+    n = max(int(n_iters), 1)
+    arrs = [dict(bnorm=np.zeros(n), pcg_iters=np.zeros(n, np.int32), pcg_ratio=np.zeros(n),
+                 setup_ran=np.zeros(n, np.int32)) for _ in range(nb)]
+    sts = (StepStats * nb)()
+    for k, a in enumerate(arrs):
+        sts[k] = StepStats(_np_ptr(a["bnorm"]).value, _np_ptr(a["pcg_iters"]).value,
+                           _np_ptr(a["pcg_ratio"]).value, _np_ptr(a["setup_ran"]).value,
+                           0, 0.0, 0.0, 0.0, 0, 0.0)
+    sys_ctx = mgpbd_batch_context(batch)
+    _prepare(sys_ctx)
+    st = lib().mgpbd_batch_step(batch, xs, vs, int(n_iters), sts if stats else None)
+    _check(sys_ctx, st)
+    out = []
+    for k, a in enumerate(arrs):
+        d = sts[k].iters_done
+        out.append(dict(bnorm=a["bnorm"][:d], pcg_iters=a["pcg_iters"][:d],
+                        pcg_ratio=a["pcg_ratio"][:d], setup_ran=a["setup_ran"][:d],
+                        iters_done=d, ms_setup=sts[k].ms_setup, ms_pcg=sts[k].ms_pcg,
+                        ms_total=sts[k].ms_total, spmv_calls=sts[k].spmv_calls,
+                        spmv_ms=sts[k].spmv_ms))
+    return out
 
 
 def mgpbd_batch_destroy(batch):
@@ -380,6 +406,32 @@ class Body:
         if self.ctx:
             mgpbd_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several bodies stepped together as one block-diagonal system."""
+
+    def __init__(self, workloads, opt: Options | None = None, device="cuda:0"):
+        self.bodies = [Body(w, opt, device) for w in workloads]
+        self.h = mgpbd_batch_create([b.ctx for b in self.bodies])
+        self.ctx = mgpbd_batch_context(self.h)
+
+    def step(self, n_iters, stats=True):
+        return mgpbd_batch_step(self.h, [b.x for b in self.bodies], [b.v for b in self.bodies],
+                                n_iters, stats)
+
+    def close(self):
+        if self.h:
+            mgpbd_batch_destroy(self.h)
+            self.h = None
+        for b in self.bodies:
+            b.close()
 
     def __del__(self):
         try:

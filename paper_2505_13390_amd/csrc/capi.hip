@@ -29,9 +29,11 @@ struct mgpbd_ctx {
   hipStream_t own = nullptr;
   hipStream_t st = nullptr;
   std::unique_ptr<Solver> solver;
-  // body (absent for solver-only contexts)
+  // bodies (none for solver-only contexts; several for the system of a batch)
   bool has_body = false;
-  int64_t nv = 0, n_edges = 0, n_vols = 0, m = 0, nnz = 0;
+  int nb = 1;
+  int64_t nv = 0, m = 0, nnz = 0;
+  std::vector<int64_t> voff{0, 0}, roff{0, 0};   // first vertex / row of each body
   double dt = 0.0, g[3] = {0, 0, 0};
   int64_t frame = 0;
   bool stale = true;
@@ -42,12 +44,21 @@ struct mgpbd_ctx {
   DevBuf<int8_t> vslot;
   DevBuf<double> w, alpha_t, rest_c, C, grad, lambda, b, old[3];
   DevBuf<int> bad;
+  // matrix-free fine operator: gradient planes, per-incidence gradients,
+  // gather scratch (FP64; FP32 copies for the mixed V-cycle)
+  DevBuf<double> mf_gp, mf_gT, mf_u;
+  DevBuf<float> mf_gp32, mf_gT32, mf_u32, mf_alpha32, mf_w32;
   std::vector<int32_t> force;
   bool have_rhs = false;
+  bool batch_owned = false;   // the system context of a batch (freed with it)
 };
 
+// A batch owns a system context whose arrays are its bodies' arrays back to
+// back (vertex, row and entry indices shifted by each body's offsets).
 struct mgpbd_batch {
   std::vector<mgpbd_ctx *> ctxs;
+  mgpbd_ctx sys;
+  DevBuf<double> pos[3], vel[3];
 };
 
 namespace {
@@ -95,6 +106,8 @@ void check_options(const mgpbd_options &o) {
   MG_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 4 || o.spmv_lanes == 8 || o.spmv_lanes == 16 ||
                  o.spmv_lanes == 32 || o.spmv_lanes == 64,
              MGPBD_E_INVALID_ARG, "spmv_lanes must be 0, 4, 8, 16, 32 or 64");
+  MG_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, MGPBD_E_INVALID_ARG,
+             "matrix_free must be 0 or 1");
 }
 
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
@@ -104,6 +117,157 @@ void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
   c->st = c->own;
   c->solver.reset(new Solver(c->opt));
   c->solver->set_stream(c->st);
+}
+
+// per-iteration arrays of a context whose pattern (F.rowptr/col, rv, ...) is set
+void alloc_state(mgpbd_ctx *c) {
+  Solver &S = *c->solver;
+  Level &F = S.L0();
+  F.n = c->m;
+  F.nnz = c->nnz;
+  F.val.alloc(c->nnz);
+  if (c->opt.precision == MGPBD_PREC_MIXED) {
+    F.val32.alloc(c->nnz);
+    S.val32_external = true;
+  }
+  S.pattern_dirty = true;
+  S.set_bodies(c->roff);
+  c->C.alloc(c->m);
+  c->grad.alloc(12 * (size_t)c->m);
+  c->lambda.alloc(c->m);
+  c->b.alloc(c->m);
+  c->bad.alloc(1);
+  for (int k = 0; k < 3; ++k) c->old[k].alloc(c->nv);
+  S.mf = MfView<double>();
+  S.mf32 = MfView<float>();
+  if (c->opt.matrix_free && c->m > 0) {
+    const int64_t n_inc = (int64_t)c->vrow.n;
+    c->mf_gp.alloc(12 * (size_t)c->m);
+    c->mf_gT.alloc(3 * (size_t)std::max<int64_t>(n_inc, 1));
+    c->mf_u.alloc(4 * (size_t)std::max<int64_t>(c->nv, 1));
+    MfView<double> v;
+    v.m = c->m; v.nv = c->nv; v.rv = c->rv.p; v.gp = c->mf_gp.p; v.alpha = c->alpha_t.p;
+    v.vptr = c->vptr.p; v.vrow = c->vrow.p; v.gT = c->mf_gT.p; v.w = c->w.p; v.u = c->mf_u.p;
+    S.mf = v;
+    if (S.mixed()) {
+      c->mf_gp32.alloc(12 * (size_t)c->m);
+      c->mf_gT32.alloc(3 * (size_t)std::max<int64_t>(n_inc, 1));
+      c->mf_u32.alloc(4 * (size_t)std::max<int64_t>(c->nv, 1));
+      c->mf_alpha32.alloc(c->m);
+      c->mf_w32.alloc(std::max<int64_t>(c->nv, 1));
+      launch_d2f(c->m, c->alpha_t.p, c->mf_alpha32.p, nullptr, c->st);
+      launch_d2f(c->nv, c->w.p, c->mf_w32.p, nullptr, c->st);
+      MfView<float> f;
+      f.m = c->m; f.nv = c->nv; f.rv = c->rv.p; f.gp = c->mf_gp32.p; f.alpha = c->mf_alpha32.p;
+      f.vptr = c->vptr.p; f.vrow = c->vrow.p; f.gT = c->mf_gT32.p; f.w = c->mf_w32.p;
+      f.u = c->mf_u32.p;
+      S.mf32 = f;
+    }
+  }
+}
+
+// One frame of Algorithm 1 for every body of c. force[k] (nullable) fixes
+// body k's PCG iteration counts; stats (nullable) holds one struct per body.
+// A body whose |b| falls below eps_b stops: later iterations solve a zero
+// right-hand side for it, which leaves its x and lambda unchanged.
+void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_iters,
+              const std::vector<const std::vector<int32_t> *> &force, mgpbd_step_stats *stats) {
+  hipStream_t st = c->st;
+  Solver &S = *c->solver;
+  const int nb = c->nb;
+  const int64_t nv = c->nv, m = c->m;
+  double *oxyz[3] = {c->old[0].p, c->old[1].p, c->old[2].p};
+  MG_HIP(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
+  for (int k = 0; k < 3; ++k) {
+    launch_check_finite(nv, xyz[k], c->bad.p, st);
+    launch_check_finite(nv, vxyz[k], c->bad.p, st);
+  }
+  int hbad = 0;
+  MG_HIP(hipMemcpyAsync(&hbad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  MG_REQUIRE(hbad == 0, MGPBD_E_INVALID_ARG, "non-finite positions or velocities");
+  Timer total, part;
+  total.start(st);
+  double ms_setup = 0.0, ms_pcg = 0.0;
+  S.spmv_calls = 0;
+  S.spmv_ms = 0.0;
+  launch_predict(nv, c->w.p, c->g, c->dt, xyz, vxyz, oxyz, st);
+  launch_fill(m, 0.0, c->lambda.p, st);
+  Level &F = S.L0();
+  std::vector<char> stopped(nb, 0);
+  std::vector<int> iters_done(nb, 0);
+  std::vector<int32_t> fv(nb, 0);
+  int n_stopped = 0;
+  for (int ite = 0; ite < n_iters && n_stopped < nb; ++ite) {
+    launch_constraints(m, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
+    const int64_t n_inc = (int64_t)c->vrow.n;
+    if (S.mf.ok())
+      launch_mf_prepare<double>(m, n_inc, c->rv.p, c->grad.p, c->vrow.p, c->vslot.p,
+                                c->mf_gp.p, c->mf_gT.p, st);
+    if (S.mf32.ok())
+      launch_mf_prepare<float>(m, n_inc, c->rv.p, c->grad.p, c->vrow.p, c->vslot.p,
+                               c->mf_gp32.p, c->mf_gT32.p, st);
+    launch_assemble(m, 16, F.rowptr.p, F.col.p, c->meta.p, c->rv.p, c->w.p, c->grad.p,
+                    c->alpha_t.p, c->C.p, c->lambda.p, F.val.p, S.mixed() ? F.val32.p : nullptr,
+                    c->b.p, st);
+    for (int k = 0; k < nb; ++k)
+      if (stopped[k] && c->roff[k + 1] > c->roff[k])
+        MG_HIP(hipMemsetAsync(c->b.p + c->roff[k], 0,
+                              sizeof(double) * (c->roff[k + 1] - c->roff[k]), st));
+    c->have_rhs = true;
+    std::vector<double> bn = S.norm2(c->b.p);
+    for (auto &v : bn) v = std::sqrt(v);
+    const int R = c->opt.reuse_interval;
+    const bool due = c->stale || !S.built || R <= 0 || (ite == 0 && (c->frame % R) == 0);
+    for (int k = 0; k < nb; ++k) {
+      if (stopped[k] || !stats) continue;
+      if (stats[k].bnorm) stats[k].bnorm[ite] = bn[k];
+      if (stats[k].setup_ran) stats[k].setup_ran[ite] = due ? 1 : 0;
+    }
+    part.start(st);
+    if (due) {
+      S.setup();
+      c->stale = false;
+    } else {
+      S.refresh();
+    }
+    ms_setup += part.stop(st);
+    for (int k = 0; k < nb; ++k) {
+      const std::vector<int32_t> *f = k < (int)force.size() ? force[k] : nullptr;
+      fv[k] = (!stopped[k] && f && ite < (int)f->size()) ? (*f)[ite] : 0;
+    }
+    part.start(st);
+    std::vector<PcgResult> pr = S.pcg(c->b.p, S.dl(), c->opt.tol, c->opt.max_pcg, fv.data());
+    ms_pcg += part.stop(st);
+    for (int k = 0; k < nb; ++k) {
+      if (stopped[k]) continue;
+      if (stats && stats[k].pcg_iters) stats[k].pcg_iters[ite] = pr[k].iters;
+      if (stats && stats[k].pcg_ratio) stats[k].pcg_ratio[ite] = pr[k].ratio;
+      MG_REQUIRE(pr[k].status != 2, MGPBD_E_BREAKDOWN,
+                 "PCG breakdown (p^T A p <= 0 or r^T z <= 0)" +
+                     (nb > 1 ? " in body " + std::to_string(k) : std::string()));
+    }
+    launch_dx_update(nv, c->vptr.p, c->vrow.p, c->vslot.p, c->grad.p, S.dl(), c->w.p,
+                     c->opt.omega_relax, xyz, st);
+    launch_lambda_add(m, c->lambda.p, S.dl(), st);
+    for (int k = 0; k < nb; ++k) {
+      if (stopped[k]) continue;
+      iters_done[k] = ite + 1;
+      if (bn[k] < c->opt.eps_b) { stopped[k] = 1; ++n_stopped; }
+    }
+  }
+  launch_velocity(nv, c->dt, xyz, oxyz, vxyz, st);
+  c->frame++;
+  double ms_total = total.stop(st);
+  if (stats)
+    for (int k = 0; k < nb; ++k) {
+      stats[k].iters_done = iters_done[k];
+      stats[k].ms_setup = ms_setup;
+      stats[k].ms_pcg = ms_pcg;
+      stats[k].ms_total = ms_total;
+      stats[k].spmv_calls = S.spmv_calls;
+      stats[k].spmv_ms = S.spmv_ms;
+    }
 }
 
 }  // namespace
@@ -134,6 +298,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->profile_spmv = 0;
   o->spmv_tile = 0;
   o->spmv_lanes = 0;
+  o->matrix_free = 1;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {
@@ -177,7 +342,9 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
     MG_REQUIRE(t.nnz < (int64_t)INT32_MAX, MGPBD_E_INVALID_ARG,
                "A has more than 2^31 entries; split the body into a batch");
     c->has_body = true;
-    c->nv = nv; c->n_edges = t.n_edges; c->n_vols = t.n_vols; c->m = t.m; c->nnz = t.nnz;
+    c->nv = nv; c->m = t.m; c->nnz = t.nnz;
+    c->voff = {0, nv};
+    c->roff = {0, t.m};
     c->dt = dt;
     for (int k = 0; k < 3; ++k) c->g[k] = gravity[k];
     const double dt2 = dt * dt;
@@ -197,23 +364,10 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
     c->w.upload(w.data(), nv, st);
     c->alpha_t.upload(at.data(), t.m, st);
     Level &F = c->solver->L0();
-    F.n = t.m;
-    F.nnz = t.nnz;
     F.rowptr.upload(t.rowptr.data(), t.rowptr.size(), st);
     F.col.upload(t.col.data(), t.col.size(), st);
-    F.val.alloc(t.nnz);
-    if (c->opt.precision == MGPBD_PREC_MIXED) {
-      F.val32.alloc(t.nnz);
-      c->solver->val32_external = true;
-    }
-    c->solver->pattern_dirty = true;
-    c->C.alloc(t.m);
-    c->grad.alloc(12 * (size_t)t.m);
-    c->lambda.alloc(t.m);
-    c->b.alloc(t.m);
+    alloc_state(c);
     c->rest_c.alloc(t.m);
-    c->bad.alloc(1);
-    for (int k = 0; k < 3; ++k) c->old[k].alloc(nv);
     // rest lengths and volumes: the constraint kernel itself at the rest
     // positions, so that C is exactly zero at rest
     DevBuf<double> rx[3];
@@ -224,7 +378,7 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
     }
     launch_fill(t.m, 0.0, c->rest_c.p, st);
     double *xyz[3] = {rx[0].p, rx[1].p, rx[2].p};
-    launch_constraints(t.m, t.n_edges, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
+    launch_constraints(t.m, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
     MG_HIP(hipMemcpyAsync(c->rest_c.p, c->C.p, sizeof(double) * t.m, hipMemcpyDeviceToDevice, st));
     std::vector<double> rc(t.m);
     c->rest_c.download(rc.data(), t.m, st);
@@ -277,75 +431,18 @@ mgpbd_status mgpbd_step(mgpbd_ctx *c, double *x, double *y, double *z, double *v
   if (!c) return MGPBD_E_INVALID_ARG;
   if (!c->has_body) { c->err = "context has no body"; return MGPBD_E_STATE; }
   if (!x || !y || !z || !vx || !vy || !vz || n_iters < 0) return MGPBD_E_INVALID_ARG;
+  if (c->nb != 1) { c->err = "context belongs to a batch"; return MGPBD_E_STATE; }
   return guard(c, [&] {
-    hipStream_t st = c->st;
-    Solver &S = *c->solver;
-    const int64_t nv = c->nv, m = c->m;
     double *xyz[3] = {x, y, z};
     double *vxyz[3] = {vx, vy, vz};
-    double *oxyz[3] = {c->old[0].p, c->old[1].p, c->old[2].p};
-    MG_HIP(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
-    for (int k = 0; k < 3; ++k) {
-      launch_check_finite(nv, xyz[k], c->bad.p, st);
-      launch_check_finite(nv, vxyz[k], c->bad.p, st);
+    std::vector<const std::vector<int32_t> *> force{&c->force};
+    try {
+      run_step(c, xyz, vxyz, n_iters, force, stats);
+    } catch (...) {
+      c->force.clear();
+      throw;
     }
-    int hbad = 0;
-    MG_HIP(hipMemcpyAsync(&hbad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    MG_HIP(hipStreamSynchronize(st));
-    MG_REQUIRE(hbad == 0, MGPBD_E_INVALID_ARG, "non-finite positions or velocities");
-    Timer total, part;
-    total.start(st);
-    double ms_setup = 0.0, ms_pcg = 0.0;
-    S.spmv_calls = 0;
-    S.spmv_ms = 0.0;
-    launch_predict(nv, c->w.p, c->g, c->dt, xyz, vxyz, oxyz, st);
-    launch_fill(m, 0.0, c->lambda.p, st);
-    Level &F = S.L0();
-    int done_iters = 0;
-    for (int ite = 0; ite < n_iters; ++ite) {
-      launch_constraints(m, c->n_edges, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
-      launch_assemble(m, c->n_edges, 16, F.rowptr.p, F.col.p, c->meta.p, c->rv.p, c->w.p,
-                      c->grad.p, c->alpha_t.p, c->C.p, c->lambda.p, F.val.p,
-                      S.mixed() ? F.val32.p : nullptr, c->b.p, st);
-      c->have_rhs = true;
-      double bn = std::sqrt(S.norm2(c->b.p, m));
-      if (stats && stats->bnorm) stats->bnorm[ite] = bn;
-      const int R = c->opt.reuse_interval;
-      bool due = c->stale || !S.built || R <= 0 || (ite == 0 && (c->frame % R) == 0);
-      if (stats && stats->setup_ran) stats->setup_ran[ite] = due ? 1 : 0;
-      part.start(st);
-      if (due) {
-        S.setup();
-        c->stale = false;
-      } else {
-        S.refresh();
-      }
-      ms_setup += part.stop(st);
-      int force = (ite < (int)c->force.size()) ? c->force[ite] : 0;
-      part.start(st);
-      PcgResult pr = S.pcg(c->b.p, S.dl(), c->opt.tol, c->opt.max_pcg, force);
-      ms_pcg += part.stop(st);
-      if (stats && stats->pcg_iters) stats->pcg_iters[ite] = pr.iters;
-      if (stats && stats->pcg_ratio) stats->pcg_ratio[ite] = pr.ratio;
-      MG_REQUIRE(pr.status != 2, MGPBD_E_BREAKDOWN, "PCG breakdown (p^T A p <= 0 or r^T z <= 0)");
-      launch_dx_update(nv, c->vptr.p, c->vrow.p, c->vslot.p, c->grad.p, S.dl(), c->w.p,
-                       c->opt.omega_relax, xyz, st);
-      launch_lambda_add(m, c->lambda.p, S.dl(), st);
-      done_iters = ite + 1;
-      if (bn < c->opt.eps_b) break;
-    }
-    launch_velocity(nv, c->dt, xyz, oxyz, vxyz, st);
-    c->frame++;
-    double ms_total = total.stop(st);
     c->force.clear();
-    if (stats) {
-      stats->iters_done = done_iters;
-      stats->ms_setup = ms_setup;
-      stats->ms_pcg = ms_pcg;
-      stats->ms_total = ms_total;
-      stats->spmv_calls = S.spmv_calls;
-      stats->spmv_ms = S.spmv_ms;
-    }
   });
 }
 
@@ -380,7 +477,7 @@ mgpbd_status mgpbd_solve(mgpbd_ctx *c, const mgpbd_csr *A, const double *b, doub
     S.setup();
     double ms_setup = t.stop(st);
     t.start(st);
-    PcgResult pr = S.pcg(b, x_out, tol, c->opt.max_pcg, 0);
+    PcgResult pr = S.pcg(b, x_out, tol, c->opt.max_pcg, nullptr)[0];
     double ms_solve = t.stop(st);
     if (stats) {
       stats->iters = pr.iters;
@@ -398,7 +495,7 @@ mgpbd_status mgpbd_solve(mgpbd_ctx *c, const mgpbd_csr *A, const double *b, doub
 }
 
 void mgpbd_destroy(mgpbd_ctx *c) {
-  if (!c) return;
+  if (!c || c->batch_owned) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
   c->solver.reset();
   hipStream_t own = c->own;
@@ -435,7 +532,7 @@ mgpbd_status mgpbd_get_level(const mgpbd_ctx *c, int32_t l, int64_t *n, int64_t 
   const Level &L = *c->solver->lev[l];
   if (n) *n = L.n;
   if (nnz) *nnz = L.nnz;
-  if (omega) *omega = L.omega;
+  if (omega) *omega = L.omega.empty() ? 0.0 : L.omega[0];
   if (n_agg) *n_agg = L.has_next ? L.n_agg : -1;
   return MGPBD_OK;
 }
@@ -518,27 +615,146 @@ mgpbd_status mgpbd_selftest_sqrt_div(int64_t n, const double *a, const double *b
 // ------------------------------------------------------------------ batch
 mgpbd_status mgpbd_batch_create(mgpbd_ctx *const *ctxs, int32_t n, mgpbd_batch **out) {
   if (!ctxs || n <= 0 || !out) return MGPBD_E_INVALID_ARG;
+  *out = nullptr;
   for (int32_t k = 0; k < n; ++k)
-    if (!ctxs[k] || !ctxs[k]->has_body) return MGPBD_E_INVALID_ARG;
-  auto *b = new (std::nothrow) mgpbd_batch();
-  if (!b) return MGPBD_E_OUT_OF_MEMORY;
-  b->ctxs.assign(ctxs, ctxs + n);
-  *out = b;
-  return MGPBD_OK;
-}
-
-mgpbd_status mgpbd_batch_step(mgpbd_batch *b, double *const *xyz, double *const *vxyz,
-                              int32_t n_iters, mgpbd_step_stats *st) {
-  if (!b || !xyz || !vxyz) return MGPBD_E_INVALID_ARG;
-  for (size_t k = 0; k < b->ctxs.size(); ++k) {
-    mgpbd_status s = mgpbd_step(b->ctxs[k], xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2],
-                                vxyz[3 * k], vxyz[3 * k + 1], vxyz[3 * k + 2], n_iters,
-                                st ? &st[k] : nullptr);
-    if (s != MGPBD_OK) return s;
+    if (!ctxs[k] || !ctxs[k]->has_body || ctxs[k]->nb != 1) return MGPBD_E_INVALID_ARG;
+  for (int32_t k = 1; k < n; ++k) {
+    const mgpbd_ctx &a = *ctxs[0], &b = *ctxs[k];
+    if (a.dt != b.dt || a.g[0] != b.g[0] || a.g[1] != b.g[1] || a.g[2] != b.g[2] ||
+        a.opt.precision != b.opt.precision)
+      return MGPBD_E_INVALID_ARG;
   }
+  auto *bt = new (std::nothrow) mgpbd_batch();
+  if (!bt) return MGPBD_E_OUT_OF_MEMORY;
+  mgpbd_ctx *c = &bt->sys;
+  mgpbd_status s = guard(c, [&] {
+    bt->ctxs.assign(ctxs, ctxs + n);
+    init_ctx(c, &ctxs[0]->opt);
+    hipStream_t st = c->st;
+    c->has_body = true;
+    c->batch_owned = true;
+    c->nb = n;
+    c->dt = ctxs[0]->dt;
+    for (int k = 0; k < 3; ++k) c->g[k] = ctxs[0]->g[k];
+    std::vector<int64_t> eoff(n + 1, 0), toff(n + 1, 0);
+    c->voff.assign(n + 1, 0);
+    c->roff.assign(n + 1, 0);
+    for (int k = 0; k < n; ++k) {
+      const mgpbd_ctx &b = *ctxs[k];
+      c->voff[k + 1] = c->voff[k] + b.nv;
+      c->roff[k + 1] = c->roff[k] + b.m;
+      eoff[k + 1] = eoff[k] + b.nnz;
+      toff[k + 1] = toff[k] + (int64_t)b.vrow.n;
+    }
+    c->nv = c->voff[n];
+    c->m = c->roff[n];
+    c->nnz = eoff[n];
+    MG_REQUIRE(c->nnz < (int64_t)INT32_MAX && c->m < (int64_t)INT32_MAX &&
+                   c->nv < (int64_t)INT32_MAX,
+               MGPBD_E_INVALID_ARG, "the batch has more than 2^31 entries");
+    Level &F = c->solver->L0();
+    c->rv.alloc(4 * (size_t)c->m);
+    c->meta.alloc(c->nnz);
+    c->vptr.alloc(c->nv + 1);
+    c->vrow.alloc(std::max<int64_t>(toff[n], 1));
+    c->vslot.alloc(std::max<int64_t>(toff[n], 1));
+    c->w.alloc(c->nv);
+    c->alpha_t.alloc(c->m);
+    c->rest_c.alloc(c->m);
+    F.rowptr.alloc(c->m + 1);
+    F.col.alloc(c->nnz);
+    auto d2d = [&](void *dst, const void *src, size_t bytes) {
+      if (bytes) MG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    };
+    for (int k = 0; k < n; ++k) {
+      const mgpbd_ctx &b = *ctxs[k];
+      const Level &Fb = b.solver->L0();
+      const int64_t v0 = c->voff[k], r0 = c->roff[k], e0 = eoff[k], t0 = toff[k];
+      launch_offset_copy(4 * b.m, b.rv.p, (int32_t)v0, c->rv.p + 4 * r0, st);
+      d2d(c->meta.p + e0, b.meta.p, sizeof(uint32_t) * b.nnz);
+      launch_offset_copy(b.m, Fb.rowptr.p, e0, F.rowptr.p + r0, st);
+      launch_offset_copy(b.nnz, Fb.col.p, (int32_t)r0, F.col.p + e0, st);
+      launch_offset_copy(b.nv, b.vptr.p, t0, c->vptr.p + v0, st);
+      launch_offset_copy((int64_t)b.vrow.n, b.vrow.p, (int32_t)r0, c->vrow.p + t0, st);
+      d2d(c->vslot.p + t0, b.vslot.p, b.vslot.n);
+      d2d(c->w.p + v0, b.w.p, sizeof(double) * b.nv);
+      d2d(c->alpha_t.p + r0, b.alpha_t.p, sizeof(double) * b.m);
+      d2d(c->rest_c.p + r0, b.rest_c.p, sizeof(double) * b.m);
+    }
+    MG_HIP(hipMemcpyAsync(F.rowptr.p + c->m, &eoff[n], sizeof(int64_t), hipMemcpyHostToDevice, st));
+    MG_HIP(hipMemcpyAsync(c->vptr.p + c->nv, &toff[n], sizeof(int64_t), hipMemcpyHostToDevice, st));
+    alloc_state(c);
+    for (int k = 0; k < 3; ++k) {
+      bt->pos[k].alloc(c->nv);
+      bt->vel[k].alloc(c->nv);
+    }
+    MG_HIP(hipStreamSynchronize(st));
+  });
+  if (s != MGPBD_OK) {
+    const std::string msg = c->err;
+    delete bt;
+    if (n > 0 && ctxs[0]) ctxs[0]->err = msg;
+    return s;
+  }
+  *out = bt;
   return MGPBD_OK;
 }
 
-void mgpbd_batch_destroy(mgpbd_batch *b) { delete b; }
+mgpbd_status mgpbd_batch_step(mgpbd_batch *bt, double *const *xyz, double *const *vxyz,
+                              int32_t n_iters, mgpbd_step_stats *stats) {
+  if (!bt || !xyz || !vxyz || n_iters < 0) return MGPBD_E_INVALID_ARG;
+  const int n = (int)bt->ctxs.size();
+  for (int k = 0; k < 3 * n; ++k)
+    if (!xyz[k] || !vxyz[k]) return MGPBD_E_INVALID_ARG;
+  mgpbd_ctx *c = &bt->sys;
+  return guard(c, [&] {
+    hipStream_t st = c->st;
+    // every body's state is copied in, stepped in one system, and copied out
+    for (int k = 0; k < n; ++k) {
+      const int64_t v0 = c->voff[k], nvk = c->voff[k + 1] - v0;
+      if (!nvk) continue;
+      for (int d = 0; d < 3; ++d) {
+        MG_HIP(hipMemcpyAsync(bt->pos[d].p + v0, xyz[3 * k + d], sizeof(double) * nvk,
+                              hipMemcpyDeviceToDevice, st));
+        MG_HIP(hipMemcpyAsync(bt->vel[d].p + v0, vxyz[3 * k + d], sizeof(double) * nvk,
+                              hipMemcpyDeviceToDevice, st));
+      }
+    }
+    double *pos[3] = {bt->pos[0].p, bt->pos[1].p, bt->pos[2].p};
+    double *vel[3] = {bt->vel[0].p, bt->vel[1].p, bt->vel[2].p};
+    std::vector<const std::vector<int32_t> *> force(n);
+    for (int k = 0; k < n; ++k) force[k] = &bt->ctxs[k]->force;
+    try {
+      run_step(c, pos, vel, n_iters, force, stats);
+    } catch (...) {
+      for (auto *b : bt->ctxs) b->force.clear();
+      throw;
+    }
+    for (auto *b : bt->ctxs) b->force.clear();
+    for (int k = 0; k < n; ++k) {
+      const int64_t v0 = c->voff[k], nvk = c->voff[k + 1] - v0;
+      if (!nvk) continue;
+      for (int d = 0; d < 3; ++d) {
+        MG_HIP(hipMemcpyAsync(xyz[3 * k + d], bt->pos[d].p + v0, sizeof(double) * nvk,
+                              hipMemcpyDeviceToDevice, st));
+        MG_HIP(hipMemcpyAsync(vxyz[3 * k + d], bt->vel[d].p + v0, sizeof(double) * nvk,
+                              hipMemcpyDeviceToDevice, st));
+      }
+    }
+    MG_HIP(hipStreamSynchronize(st));
+  });
+}
+
+mgpbd_ctx *mgpbd_batch_context(mgpbd_batch *bt) { return bt ? &bt->sys : nullptr; }
+
+void mgpbd_batch_destroy(mgpbd_batch *bt) {
+  if (!bt) return;
+  mgpbd_ctx *c = &bt->sys;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  c->solver.reset();
+  hipStream_t own = c->own;
+  delete bt;
+  if (own) (void)hipStreamDestroy(own);
+}
 
 }  // extern "C"

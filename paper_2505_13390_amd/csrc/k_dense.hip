@@ -4,6 +4,7 @@
 // inverse as a dense product. The trailing updates of the factorisation and
 // the product Y^T Y that forms the inverse run on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64) in 16 x 16 tiles.
+#include "seg.hpp"
 #include "setup.hpp"
 
 namespace mgpbd {
@@ -48,9 +49,10 @@ __device__ __forceinline__ v4d mfma_tile_nt(const double *__restrict__ M, int64_
 // One workgroup of 256 threads (4 waves). n is padded by the caller to a
 // multiple of 16 with an identity block (the padding does not change the
 // inverse of the leading n x n part).
-__global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, double *__restrict__ D,
-                                                      double *__restrict__ Y,
-                                                      double *__restrict__ Ainv, int *status) {
+// Factorisation + inverse by one workgroup; returns nonzero (in every thread)
+// when a pivot is not positive.
+__device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
+                                  double *__restrict__ Y, double *__restrict__ Ainv) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, nw = nthr >> 6, lane = tid & 63;
   __shared__ int bad;
@@ -102,10 +104,7 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, dou
     }
   }
   __syncthreads();
-  if (bad) {
-    if (tid == 0) *status = 1;
-    return;
-  }
+  if (bad) return 1;
   // ---- Y = L^-1 (lower): column c solved by one thread ----
   for (int64_t c = tid; c < np; c += nthr) {
     for (int64_t i = 0; i < c; ++i) Y[i * np + c] = 0.0;
@@ -137,7 +136,14 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, dou
       if (rr < n && cl < n) Ainv[rr * n + cl] = acc[q];
     }
   }
-  if (tid == 0) *status = 0;
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, double *__restrict__ D,
+                                                      double *__restrict__ Y,
+                                                      double *__restrict__ Ainv, int *status) {
+  int bad = chol_inverse_block(n, np, D, Y, Ainv);
+  if (threadIdx.x == 0) *status = bad;
 }
 
 __global__ void k_pad_dense(int64_t n, int64_t np, const double *__restrict__ D,
@@ -161,5 +167,52 @@ void launch_chol_inverse(int64_t n, double *D, double *Y, double *Ainv, int *sta
   k_pad_dense<<<blocks_for(np * np, kBlock), kBlock, 0, s>>>(n, np, D, Pd);
   k_chol_inverse<<<1, 256, 0, s>>>(n, np, Pd, Y, Ainv, status);
 }
+
+// ------------------------------------------------------------ dense batch
+__global__ void k_dense_init_batch(const DenseJob *jobs, const int64_t *__restrict__ rp,
+                                     const int32_t *__restrict__ col,
+                                     const double *__restrict__ val, double *scratch) {
+  const DenseJob j = jobs[blockIdx.y];
+  const int64_t np = (j.n + 15) / 16 * 16;
+  double *P = scratch + j.scratch + np * np;   // padded matrix
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < np * np;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = idx / np, k = idx % np;
+    P[idx] = (i == k && i >= j.n) ? 1.0 : 0.0;
+  }
+}
+__global__ void k_dense_scatter_batch(const DenseJob *jobs, const int64_t *__restrict__ rp,
+                                      const int32_t *__restrict__ col,
+                                      const double *__restrict__ val, double *scratch) {
+  const DenseJob j = jobs[blockIdx.y];
+  const int64_t np = (j.n + 15) / 16 * 16;
+  double *P = scratch + j.scratch + np * np;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gi = j.row0 + i;
+    for (int64_t e = rp[gi]; e < rp[gi + 1]; ++e) P[i * np + (col[e] - j.row0)] = val[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chol_inverse_batch(const DenseJob *jobs, double *scratch,
+                                                            double *ainv, int *status) {
+  const DenseJob j = jobs[blockIdx.x];
+  const int64_t np = (j.n + 15) / 16 * 16;
+  double *Y = scratch + j.scratch;
+  double *P = Y + np * np;
+  int bad = chol_inverse_block(j.n, np, P, Y, ainv + j.ainv);
+  if (threadIdx.x == 0 && bad) atomicExch(status, 1);
+}
+
+void launch_dense_factor_batch(int njobs, const DenseJob *jobs, const int64_t *rp,
+                               const int32_t *col, const double *val, double *scratch,
+                               double *ainv, int *status, hipStream_t s) {
+  if (njobs <= 0) return;
+  dim3 g(64, njobs);
+  k_dense_init_batch<<<g, kBlock, 0, s>>>(jobs, rp, col, val, scratch);
+  k_dense_scatter_batch<<<g, kBlock, 0, s>>>(jobs, rp, col, val, scratch);
+  k_chol_inverse_batch<<<njobs, 256, 0, s>>>(jobs, scratch, ainv, status);
+}
+
 
 }  // namespace mgpbd

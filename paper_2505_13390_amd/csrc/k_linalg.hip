@@ -5,6 +5,7 @@
 // reductions and a device-resident control block (no host round trip per
 // iteration; every kernel returns at once when the solve is finished).
 #include "kernels.hpp"
+#include "rowops.hpp"
 
 namespace mgpbd {
 
@@ -23,39 +24,6 @@ int lanes_for_rowlen(double mean) {
     case 32: LAUNCH(32); break;      \
     default: LAUNCH(64); break;      \
   }
-
-// ------------------------------------------------------------ row ops
-// What a CSR pass does with the row sum s = (A x)_i. Every pass of the
-// solving phase (product, smoother sweep, residual, PCG product + dot) is one
-// of these epilogues on one of the two product kernels below.
-template <class T>
-struct OpSpmv {
-  T *y;
-  __device__ void operator()(int64_t i, T s, double &) const { y[i] = s; }
-};
-template <class T>
-struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi)
-  const T *dinv, *r, *zi;
-  T omega;
-  T *zo;
-  __device__ void operator()(int64_t i, T s, double &) const {
-    zo[i] = zi[i] + omega * ((r[i] - s) * dinv[i]);
-  }
-};
-template <class T>
-struct OpResidual {  // res = r - A z
-  const T *r;
-  T *res;
-  __device__ void operator()(int64_t i, T s, double &) const { res[i] = r[i] - s; }
-};
-struct OpPcgDot {  // q = A p, accumulate p^T q
-  const double *p;
-  double *q;
-  __device__ void operator()(int64_t i, double s, double &acc) const {
-    q[i] = s;
-    acc += p[i] * s;
-  }
-};
 
 // Row-group kernel: G lanes per row, strided loads, fixed-tree lane sum.
 template <int G, class T, class Op>
@@ -209,25 +177,25 @@ int launch_spmv_dot_partials(const CsrView<double> &A, const double *p, double *
 
 // ------------------------------------------------------------ smoother
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_jacobi_first(int64_t n, const T *__restrict__ dinv,
-                                                         const T *__restrict__ r, T omega,
+__global__ __launch_bounds__(kBlock) void k_jacobi_first(int64_t n, const T *__restrict__ wdinv,
+                                                         const T *__restrict__ r,
                                                          T *__restrict__ z, const int *done) {
   if (done && *done) return;
   int64_t lo, hi;
   block_range(n, lo, hi);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) z[i] = omega * (r[i] * dinv[i]);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) z[i] = r[i] * wdinv[i];
 }
 
 template <class T>
-void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z, const int *done,
+void launch_jacobi_first(int64_t n, const T *wdinv, const T *r, T *z, const int *done,
                          hipStream_t s) {
   if (n == 0) return;
-  k_jacobi_first<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dinv, r, omega, z, done);
+  k_jacobi_first<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, wdinv, r, z, done);
 }
 template <class T>
-void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega, const T *zi, T *zo,
+void launch_jacobi(const CsrView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                    const int *done, hipStream_t s) {
-  launch_pass<T>(A, zi, OpJacobi<T>{dinv, r, zi, omega, zo}, done, nullptr, s);
+  launch_pass<T>(A, zi, OpJacobi<T>{wdinv, r, zi, zo}, done, nullptr, s);
 }
 template <class T>
 void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
@@ -465,6 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *pa
     else ctl->alpha = ctl->rho / tot[0];
   }
 }
+void launch_fin_pq(PcgCtl *ctl, const double *partials, int nparts, hipStream_t s) {
+  k_fin_pq<<<1, kBlock, 0, s>>>(ctl, partials, nparts);
+}
 void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
                          RedBuf rb, hipStream_t s) {
   const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field
@@ -698,9 +669,9 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
 // explicit instantiations
 #define MG_INST(T)                                                                                  \
   template void launch_spmv<T>(const CsrView<T> &, const T *, T *, hipStream_t);                    \
-  template void launch_jacobi_first<T>(int64_t, const T *, const T *, T, T *, const int *,          \
+  template void launch_jacobi_first<T>(int64_t, const T *, const T *, T *, const int *,             \
                                        hipStream_t);                                                \
-  template void launch_jacobi<T>(const CsrView<T> &, const T *, const T *, T, const T *, T *,       \
+  template void launch_jacobi<T>(const CsrView<T> &, const T *, const T *, const T *, T *,          \
                                  const int *, hipStream_t);                                         \
   template void launch_residual<T>(const CsrView<T> &, const T *, const T *, T *, const int *,      \
                                    hipStream_t);                                                    \

@@ -34,7 +34,7 @@ void launch_predict(int64_t nv, const double *w, const double *g, double dt, dou
 // C and gradient of each row. Edge (i, j): C = |x_i - x_j| - L0, g_i = n,
 // g_j = -n. Volume (a, b, c, d): V = e1.(e2 x e3)/6, C = V - V0,
 // g_b = (e2 x e3)/6, g_c = (e3 x e1)/6, g_d = (e1 x e2)/6, g_a = -(g_b + g_c + g_d).
-__global__ void k_constraints(int64_t m, int64_t n_edges, const int32_t *__restrict__ rv,
+__global__ void k_constraints(int64_t m, const int32_t *__restrict__ rv,
                               const double *__restrict__ rest_c, const double *__restrict__ x,
                               const double *__restrict__ y, const double *__restrict__ z,
                               double *__restrict__ C, double *__restrict__ grad) {
@@ -45,7 +45,7 @@ __global__ void k_constraints(int64_t m, int64_t n_edges, const int32_t *__restr
 #pragma unroll
   for (int k = 0; k < 12; ++k) g[k] = 0.0;
   double val;
-  if (r < n_edges) {
+  if (v[2] < 0) {   // edge rows pad slots 2 and 3 with -1
     int32_t i = v[0], j = v[1];
     double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
     double len = sqrt((dx * dx + dy * dy) + dz * dz);
@@ -81,10 +81,10 @@ __global__ void k_constraints(int64_t m, int64_t n_edges, const int32_t *__restr
 #pragma unroll
   for (int k = 0; k < 12; ++k) go[k] = g[k];
 }
-void launch_constraints(int64_t m, int64_t n_edges, const int32_t *rv, const double *rest_c,
+void launch_constraints(int64_t m, const int32_t *rv, const double *rest_c,
                         const double *const *xyz, double *C, double *grad, hipStream_t s) {
   if (m)
-    k_constraints<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, n_edges, rv, rest_c, xyz[0], xyz[1],
+    k_constraints<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, rv, rest_c, xyz[0], xyz[1],
                                                            xyz[2], C, grad);
 }
 
@@ -93,7 +93,7 @@ void launch_constraints(int64_t m, int64_t n_edges, const int32_t *rv, const dou
 // (slot in c | slot in d << 2) of the t-th shared vertex in ascending vertex id.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_assemble(
-    int64_t m, int64_t n_edges, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+    int64_t m, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const uint32_t *__restrict__ meta, const int32_t *__restrict__ rv,
     const double *__restrict__ w, const double *__restrict__ grad,
     const double *__restrict__ alpha_t, const double *__restrict__ C,
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
     if (c >= hi) continue;
     const double *gc = grad + 12 * c;
     const int32_t *vc = rv + 4 * c;
-    const int kc = c < n_edges ? 2 : 4;
+    const int kc = vc[2] < 0 ? 2 : 4;
     for (int64_t e = rp[c] + sub; e < rp[c + 1]; e += G) {
       uint32_t code = meta[e];
       double acc;
@@ -139,14 +139,14 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
     if (sub == 0) b[c] = -C[c] - alpha_t[c] * lambda[c];
   }
 }
-void launch_assemble(int64_t m, int64_t n_edges, int lanes, const int64_t *rp, const int32_t *col,
+void launch_assemble(int64_t m, int lanes, const int64_t *rp, const int32_t *col,
                      const uint32_t *meta, const int32_t *rv, const double *w, const double *grad,
                      const double *alpha_t, const double *C, const double *lambda, double *val,
                      float *val32, double *b, hipStream_t s) {
   if (!m) return;
   int grid = grid_for(m * lanes, kBlock);
 #define L_(G)                                                                                   \
-  k_assemble<G><<<grid, kBlock, 0, s>>>(m, n_edges, rp, col, meta, rv, w, grad, alpha_t, C, \
+  k_assemble<G><<<grid, kBlock, 0, s>>>(m, rp, col, meta, rv, w, grad, alpha_t, C, \
                                         lambda, val, val32, b)
   switch (lanes) {
     case 8: L_(8); break;
@@ -191,6 +191,26 @@ __global__ void k_axpy_inplace(int64_t n, double *__restrict__ a, const double *
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = a[i] + d[i];
 }
+// concatenation of bodies: index arrays shifted by the offset of their body
+__global__ void k_offset_i32(int64_t n, const int32_t *__restrict__ in, int32_t add,
+                             int32_t *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t v = in[i];
+  out[i] = v >= 0 ? v + add : v;
+}
+__global__ void k_offset_i64(int64_t n, const int64_t *__restrict__ in, int64_t add,
+                             int64_t *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] + add;
+}
+void launch_offset_copy(int64_t n, const int32_t *in, int32_t add, int32_t *out, hipStream_t s) {
+  if (n) k_offset_i32<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, in, add, out);
+}
+void launch_offset_copy(int64_t n, const int64_t *in, int64_t add, int64_t *out, hipStream_t s) {
+  if (n) k_offset_i64<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, in, add, out);
+}
+
 void launch_lambda_add(int64_t m, double *lambda, const double *dl, hipStream_t s) {
   if (m) k_axpy_inplace<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, lambda, dl);
 }

@@ -37,11 +37,11 @@ template <class T> void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipSt
 // q = A p and the partial sums of p^T q (one per block of `grid`); returns grid
 int launch_spmv_dot_partials(const CsrView<double> &A, const double *p, double *q,
                              const int *done, double *partials, hipStream_t s);
-// z = omega D^-1 r (first sweep from z = 0)
-template <class T> void launch_jacobi_first(int64_t n, const T *dinv, const T *r, T omega, T *z,
+// z = omega D^-1 r (first sweep from z = 0); wdinv = omega D^-1 per row
+template <class T> void launch_jacobi_first(int64_t n, const T *wdinv, const T *r, T *z,
                                             const int *done, hipStream_t s);
 // zo = zi + omega D^-1 (r - A zi)
-template <class T> void launch_jacobi(const CsrView<T> &A, const T *dinv, const T *r, T omega,
+template <class T> void launch_jacobi(const CsrView<T> &A, const T *wdinv, const T *r,
                                       const T *zi, T *zo, const int *done, hipStream_t s);
 // res = r - A z
 template <class T> void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res,
@@ -75,6 +75,8 @@ void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double 
                      hipStream_t s);
 void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
                        double *zold, bool flexible, RedBuf rb, hipStream_t s);
+// finisher of p^T A p: pq, alpha (or breakdown) from nparts block partials
+void launch_fin_pq(PcgCtl *ctl, const double *partials, int nparts, hipStream_t s);
 void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
                          RedBuf rb, hipStream_t s);
 void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,

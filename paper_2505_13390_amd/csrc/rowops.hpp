@@ -1,0 +1,39 @@
+// Row epilogues shared by the CSR passes and the matrix-free passes of the
+// fine level: what a pass does with the row sum s = (A x)_i.
+#pragma once
+
+#include "devutil.hpp"
+
+namespace mgpbd {
+
+// Every pass of the solving phase (product, smoother sweep, residual, PCG
+// product + dot) is one of these epilogues on a product kernel.
+template <class T>
+struct OpSpmv {
+  T *y;
+  __device__ void operator()(int64_t i, T s, double &) const { y[i] = s; }
+};
+template <class T>
+struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi), wdinv = omega D^-1 per row
+  const T *wdinv, *r, *zi;
+  T *zo;
+  __device__ void operator()(int64_t i, T s, double &) const {
+    zo[i] = zi[i] + (r[i] - s) * wdinv[i];
+  }
+};
+template <class T>
+struct OpResidual {  // res = r - A z
+  const T *r;
+  T *res;
+  __device__ void operator()(int64_t i, T s, double &) const { res[i] = r[i] - s; }
+};
+struct OpPcgDot {  // q = A p, accumulate p^T q
+  const double *p;
+  double *q;
+  __device__ void operator()(int64_t i, double s, double &acc) const {
+    q[i] = s;
+    acc += p[i] * s;
+  }
+};
+
+}  // namespace mgpbd

@@ -22,19 +22,31 @@ Solver::Solver(const mgpbd_options &o) : opt(o) {
   lev.emplace_back(new Level());
   nlev = 1;
   ctl.alloc(1);
-  red_partials.alloc(2 * (size_t)kMaxGrid);
-  red_ticket.alloc(1);
-  MG_HIP(hipMemset(red_ticket.p, 0, sizeof(unsigned)));
+  all_done.alloc(1);
+  red_partials.alloc(2 * (size_t)kMaxGrid + 64);
   dscal.alloc(16);
   flags.alloc(kNumFlags);
   amax.alloc(1);
-  MG_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
+  ensure_pinned(4096);
 }
 
 Solver::~Solver() {
   invalidate_graph();
   for (auto e : ev) (void)hipEventDestroy(e);
   if (pinned) (void)hipHostFree(pinned);
+}
+
+void Solver::ensure_pinned(size_t bytes) {
+  if (bytes <= pinned_bytes) return;
+  if (pinned) (void)hipHostFree(pinned);
+  pinned = nullptr;
+  pinned_bytes = 0;
+  MG_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
+  pinned_bytes = bytes;
+}
+
+void Solver::ensure_partials(int nblk) {
+  red_partials.reserve(2 * (size_t)std::max(nblk, kMaxGrid) + 64);
 }
 
 void Solver::set_stream(hipStream_t s) {
@@ -50,29 +62,57 @@ void Solver::invalidate_graph() {
   graph_ok = false;
 }
 
+void Solver::set_bodies(const std::vector<int64_t> &offsets) {
+  MG_REQUIRE(offsets.size() >= 2 && offsets.front() == 0, MGPBD_E_INVALID_ARG, "body offsets");
+  for (size_t k = 1; k < offsets.size(); ++k)
+    MG_REQUIRE(offsets[k] >= offsets[k - 1], MGPBD_E_INVALID_ARG, "body offsets must ascend");
+  nb = (int)offsets.size() - 1;
+  Level &F = L0();
+  F.seg = offsets;
+  F.body.resize(nb);
+  for (int k = 0; k < nb; ++k) F.body[k] = k;
+  built = false;
+  invalidate_graph();
+}
+
+int Solver::body_levels(int k) const {
+  int d = 0;
+  for (int l = 0; l < nlev; ++l)
+    if (std::find(lev[l]->body.begin(), lev[l]->body.end(), k) != lev[l]->body.end()) d = l + 1;
+  return d;
+}
+
+// with one body the V-cycle kernels read that body's control block directly
 const int *Solver::done_ptr() const {
-  return reinterpret_cast<const int *>(reinterpret_cast<const char *>(ctl.p) +
-                                       offsetof(PcgCtl, done));
+  if (nb == 1)
+    return reinterpret_cast<const int *>(reinterpret_cast<const char *>(ctl.p) +
+                                         offsetof(PcgCtl, done));
+  return all_done.p;
 }
 
 void Solver::reset_flags() { MG_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * kNumFlags, st)); }
 
-int Solver::read_flag(int k) {
-  int *h = static_cast<int *>(pinned);
-  MG_HIP(hipMemcpyAsync(h, flags.p + k, sizeof(int), hipMemcpyDeviceToHost, st));
+int Solver::read_flag(int k) { return read_dev(flags.p + k, st, pinned); }
+
+std::vector<double> Solver::norm2(const double *v) {
+  Level &F = L0();
+  if (F.seg.empty() || F.seg.back() != F.n) set_bodies({0, F.n});
+  if (F.tab.off != F.seg) F.tab.build(F.seg, st);
+  SegTab t = F.tab.view();
+  ensure_partials(t.nblk);
+  dscal.reserve(std::max<size_t>(16, 3 * (size_t)nb + 8));
+  launch_s_dot(t, v, v, dscal.p, partials(), st);
+  std::vector<double> out(nb);
+  MG_HIP(hipMemcpyAsync(out.data(), dscal.p, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
-  return *h;
-}
-
-
-double Solver::norm2(const double *v, int64_t n) {
-  launch_dot(n, v, v, dscal.p + 8, rb(), st);
-  return read_dev(dscal.p + 8, st, pinned);
+  return out;
 }
 
 // ------------------------------------------------------------------ setup
 void Solver::finish_level(int l) {
   Level &L = *lev[l];
+  L.tab.build(L.seg, st);
+  ensure_partials(L.tab.view().nblk);
   if (l > 0 || pattern_dirty) {
     L.diagpos.alloc(L.n);
     reset_flags();
@@ -87,9 +127,10 @@ void Solver::finish_level(int l) {
   }
   L.diag.alloc(L.n);
   L.dinv.alloc(L.n);
-  if (mixed()) L.dinv32.alloc(L.n);
+  L.wdinv.alloc(L.n);
+  if (mixed()) L.wdinv32.alloc(L.n);
   reset_flags();
-  launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, mixed() ? L.dinv32.p : nullptr,
+  launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, nullptr,
                       flags.p + kFBadDiag, st);
   MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN,
              "level " + std::to_string(l) + " has a non-positive diagonal entry");
@@ -97,14 +138,18 @@ void Solver::finish_level(int l) {
   L.r.alloc(L.n); L.z.alloc(L.n); L.t.alloc(L.n); L.res.alloc(L.n);
   if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); L.res32.alloc(L.n); }
   power_omega(l);
+  L.d_omega.upload(L.omega.data(), L.omega.size(), st);
+  launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p, mixed() ? L.wdinv32.p : nullptr,
+                 st);
 }
 
 // Autotuner of the CSR passes: on large levels, time one product for each
-// variant (lanes per row of the row-group kernel; tile size of the LDS stream
-// kernel) and keep the fastest, separately for FP64 and FP32 values.
+// variant (lanes per row of the row-group kernel; tile size and load kind of
+// the LDS stream kernel) and keep the fastest, separately for FP64 and FP32.
 void Solver::tune_lanes(int l) {
   Level &L = *lev[l];
   L.tile = L.tile32 = 0;
+  L.nt = L.nt32 = false;
   if (opt.spmv_lanes > 0) L.lanes = L.lanes32 = opt.spmv_lanes;
   if (opt.spmv_tile > 0 && L.n > 0) {
     std::vector<int64_t> hrp(L.n + 1), part;
@@ -173,7 +218,10 @@ void Solver::tune_lanes(int l) {
   L.lanes = c.lanes;
   L.tile = c.tile;
   L.nt = c.nt;
-  if (c.tile) { L.tiles.upload(c.part.data(), c.part.size(), st); L.ntiles = (int64_t)c.part.size() - 1; }
+  if (c.tile) {
+    L.tiles.upload(c.part.data(), c.part.size(), st);
+    L.ntiles = (int64_t)c.part.size() - 1;
+  }
   if (do32) {
     const Cand &c32 = cands[pick32];
     L.lanes32 = c32.lanes;
@@ -187,32 +235,42 @@ void Solver::tune_lanes(int l) {
   MG_HIP(hipStreamSynchronize(st));
 }
 
-// omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min), lambda_max by the
-// power method and a Rayleigh quotient (Sec. 4.5)
+// omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min) for each body,
+// lambda_max from the power method and a Rayleigh quotient (Sec. 4.5)
 void Solver::power_omega(int l) {
   Level &L = *lev[l];
-  if (L.n == 0) { L.omega = 0.0; return; }
-  uint64_t salt = stream_salt(opt.seed, kStreamPowerStart);
+  const int ns = (int)L.seg.size() - 1;
+  L.omega.assign(ns, 0.0);
+  if (L.n == 0) return;
+  SegTab t = L.tab.view();
+  dscal.reserve(std::max<size_t>(16, 3 * (size_t)ns + 8));
+  double *nrm2 = dscal.p, *ray = dscal.p + ns;
   double *v = L.r.p, *w = L.t.p;
-  launch_pow_init(L.n, salt, l, v, st);
+  launch_s_pow_init(t, stream_salt(opt.seed, kStreamPowerStart), l, v, st);
   CsrView<double> A = L.view();
   for (int it = 0; it < opt.power_iters; ++it) {
     launch_spmv<double>(A, v, w, st);
-    launch_pow_scale(L.n, w, L.diag.p, dscal.p, rb(), st);
-    launch_pow_normalize(L.n, w, dscal.p, v, st);
+    launch_s_pow_scale(t, w, L.diag.p, nrm2, partials(), st);
+    launch_s_pow_normalize(t, w, nrm2, v, st);
   }
   launch_spmv<double>(A, v, w, st);
-  launch_rayleigh(L.n, v, w, L.diag.p, dscal.p + 1, rb(), st);
-  double *h = static_cast<double *>(pinned);
-  MG_HIP(hipMemcpyAsync(h, dscal.p + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  launch_s_rayleigh(t, v, w, L.diag.p, ray, partials(), st);
+  std::vector<double> h(2 * (size_t)ns);
+  MG_HIP(hipMemcpyAsync(h.data(), ray, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
-  double lmax = h[0] / h[1];
-  L.omega = 2.0 / (opt.lmax_scale * lmax + opt.lambda_min);
+  for (int k = 0; k < ns; ++k) {
+    double lmax = h[2 * k] / h[2 * k + 1];
+    L.omega[k] = 2.0 / (opt.lmax_scale * lmax + opt.lambda_min);
+  }
 }
 
-void Solver::aggregate(int l) {
+// Aggregation of every body that coarsens further (Sec. 4.1); rows of bodies
+// that end on this level count as isolated and join no aggregate. Returns the
+// first aggregate of each body (size nseg + 1).
+std::vector<int64_t> Solver::aggregate(int l) {
   Level &L = *lev[l];
   const int64_t n = L.n;
+  const int ns = (int)L.seg.size() - 1;
   CsrView<double> A = L.view();
   strong.reserve(L.nnz);
   conn.reserve(n);
@@ -220,7 +278,10 @@ void Solver::aggregate(int l) {
   m1.reserve(n);
   const double theta2 = opt.theta * opt.theta;
   launch_strong(A, L.diag.p, theta2, strong.p, conn.p, st);
-  launch_mis_init(n, conn.p, stream_salt(opt.seed, kStreamAggPrio), l, key.p, st);
+  for (int k = 0; k < ns; ++k)
+    if (L.terminal[k] && L.seg[k + 1] > L.seg[k])
+      launch_fill_u8(L.seg[k + 1] - L.seg[k], 0, conn.p + L.seg[k], st);
+  launch_s_mis_init(L.tab.view(), conn.p, stream_salt(opt.seed, kStreamAggPrio), l, key.p, st);
   for (int round = 0;; ++round) {
     MG_REQUIRE(round < 100000, MGPBD_E_SETUP, "aggregation did not terminate");
     reset_flags();
@@ -231,31 +292,48 @@ void Solver::aggregate(int l) {
   ltmp.reserve(n + 1);
   launch_root_flags(n, key.p, itmp.p, st);
   scan_exclusive_i32_to_i64(itmp.p, ltmp.p, n, scan_tmp, st);
-  L.n_agg = read_dev(ltmp.p + n, st, pinned);
+  // aggregates are numbered by ascending root row, so each body's aggregates
+  // are the roots ranked inside its row range
+  std::vector<int64_t> first(ns + 1);
+  if (ns == 1) {
+    first[0] = 0;
+    first[1] = read_dev(ltmp.p + n, st, pinned);
+  } else {
+    std::vector<int64_t> rank(n + 1);
+    ltmp.download(rank.data(), n + 1, st);
+    MG_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k <= ns; ++k) first[k] = rank[L.seg[k]];
+  }
+  L.n_agg = first[ns];
   L.agg.alloc(n);
   itmp2.reserve(n);
   launch_pass1(A, strong.p, key.p, ltmp.p, itmp2.p, st);
   launch_pass2(A, strong.p, conn.p, itmp2.p, L.agg.p, st);
+  return first;
 }
 
-// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|),
-// then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
+// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|)
+// of its body, then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
 void Solver::candidate0() {
   Level &L = *lev[0];
   const int64_t n = L.n;
+  const int ns = (int)L.seg.size() - 1;
   L.B.alloc(n);
   if (opt.b_mode == 1) {
     launch_fill(n, 1.0, L.B.p, st);
     return;
   }
   CsrView<double> A = L.view();
-  MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long), st));
-  launch_absmax(L.nnz, L.val.p, amax.p, st);
-  launch_candidate_init(n, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
-  // greedy colouring (Jones-Plassmann rounds)
+  SegTab t = L.tab.view();
+  amax.reserve(ns);
+  MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * ns, st));
+  launch_s_absmax(t, L.rowptr.p, L.val.p, amax.p, st);
+  launch_s_candidate_init(t, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
+  // greedy colouring (Jones-Plassmann rounds); keys from body-local indices
+  // colour each body as if it were alone
   key.reserve(n);
   L.color.alloc(n);
-  launch_color_keys(n, stream_salt(opt.seed, kStreamColorPrio), key.p, st);
+  launch_s_color_keys(t, stream_salt(opt.seed, kStreamColorPrio), key.p, st);
   launch_fill_i32(n, -1, L.color.p, st);
   for (int round = 0;; ++round) {
     MG_REQUIRE(round < 1000000, MGPBD_E_SETUP, "colouring did not terminate");
@@ -288,6 +366,7 @@ void Solver::candidate0() {
     for (int c = 0; c < L.n_colors; ++c)
       launch_gs_color(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
                       L.diag.p, L.B.p, st);
+  MG_HIP(hipStreamSynchronize(st));
 }
 
 void Solver::build_members(int l) {
@@ -354,18 +433,64 @@ void Solver::galerkin_numeric(int l) {
                      L.col.p, L.val.p, L.p.p, C.val.p, mixed() ? C.val32.p : nullptr, st);
 }
 
-void Solver::factor_last() {
-  Level &L = *lev[nlev - 1];
-  nd = L.n;
-  int64_t np = (nd + 15) / 16 * 16;
-  dense.reserve(std::max<int64_t>(nd * nd, 1));
-  dscratch.reserve(std::max<int64_t>(2 * np * np, 1));
-  Ainv.reserve(std::max<int64_t>(nd * nd, 1));
-  launch_csr_to_dense(nd, L.rowptr.p, L.col.p, L.val.p, dense.p, st);
+// Every body's last level is solved by an explicit inverse when it has at
+// most dense_max rows; otherwise (all rows isolated, or the level cap) the
+// smoother is that body's last-level solver. A stalled coarsening that ends
+// above dense_max is a setup failure.
+void Solver::plan_dense() {
+  int64_t ainv_off = 0, scratch_off = 0;
+  for (int l = 0; l < nlev; ++l) {
+    Level &L = *lev[l];
+    L.jobs.clear();
+    const int ns = (int)L.seg.size() - 1;
+    bool any_smooth = false;
+    for (int k = 0; k < ns; ++k) {
+      const bool last = (l == nlev - 1) || L.terminal[k];
+      if (!last) { any_smooth = true; continue; }
+      const int64_t nk = L.seg[k + 1] - L.seg[k];
+      if (nk == 0) continue;
+      if (nk <= opt.dense_max) {
+        DenseJob j;
+        j.row0 = L.seg[k];
+        j.n = nk;
+        j.ainv = ainv_off;
+        j.scratch = scratch_off;
+        j.nnz0 = 0;
+        const int64_t np = (nk + 15) / 16 * 16;
+        ainv_off += nk * nk;
+        scratch_off += 2 * np * np;
+        L.jobs.push_back(j);
+      } else {
+        MG_REQUIRE(!stalled[L.body[k]], MGPBD_E_SETUP,
+                   "coarsening stalled with " + std::to_string(nk) + " rows above dense_max");
+        any_smooth = true;
+      }
+    }
+    L.smooth_here = any_smooth;
+    L.job_rows = 0;
+    std::vector<int64_t> start;
+    for (auto &j : L.jobs) { start.push_back(L.job_rows); L.job_rows += j.n; }
+    start.push_back(L.job_rows);
+    if (!L.jobs.empty()) {
+      L.d_jobs.upload(L.jobs.data(), L.jobs.size(), st);
+      L.d_jobstart.upload(start.data(), start.size(), st);
+    }
+  }
+  Ainv.reserve(std::max<int64_t>(ainv_off, 1));
+  dscratch.reserve(std::max<int64_t>(scratch_off, 1));
+  MG_HIP(hipStreamSynchronize(st));
+}
+
+void Solver::factor_dense() {
   reset_flags();
-  launch_chol_inverse(nd, dense.p, dscratch.p, Ainv.p, flags.p + kFChol, st);
+  for (int l = 0; l < nlev; ++l) {
+    Level &L = *lev[l];
+    if (L.jobs.empty()) continue;
+    launch_dense_factor_batch((int)L.jobs.size(), L.d_jobs.p, L.rowptr.p, L.col.p, L.val.p,
+                              dscratch.p, Ainv.p, flags.p + kFChol, st);
+  }
   MG_REQUIRE(read_flag(kFChol) == 0, MGPBD_E_BREAKDOWN,
-             "coarsest level is not positive definite");
+             "a coarsest level is not positive definite");
 }
 
 void Solver::setup() {
@@ -373,6 +498,7 @@ void Solver::setup() {
   built = false;
   while (lev.size() > 1) lev.pop_back();
   Level &F = *lev[0];
+  if (F.seg.empty() || F.seg.back() != F.n) set_bodies({0, F.n});
   F.has_next = false;
   F.n_agg = 0;
   MG_REQUIRE(opt.max_levels >= 1 && opt.max_levels <= 32, MGPBD_E_INVALID_ARG,
@@ -381,15 +507,30 @@ void Solver::setup() {
     F.val32.alloc(F.nnz);
     launch_d2f(F.nnz, F.val.p, F.val32.p, nullptr, st);
   }
-  bool force_last = false, stalled = false;
+  force_last.assign(nb, 0);
+  stalled.assign(nb, 0);
   nlev = 1;
   for (int l = 0;; ++l) {
     Level &L = *lev[l];
     nlev = l + 1;
+    const int ns = (int)L.seg.size() - 1;
     finish_level(l);
-    if (force_last || L.n <= opt.coarse_max || nlev >= opt.max_levels) break;
-    aggregate(l);
-    if (L.n_agg == 0) break;
+    L.has_next = false;
+    L.terminal.assign(ns, 0);
+    bool any = false;
+    for (int k = 0; k < ns; ++k) {
+      const int64_t nk = L.seg[k + 1] - L.seg[k];
+      L.terminal[k] = force_last[L.body[k]] || nk <= opt.coarse_max || nlev >= opt.max_levels;
+      any = any || !L.terminal[k];
+    }
+    if (!any) break;
+    std::vector<int64_t> first = aggregate(l);
+    bool cont = false;
+    for (int k = 0; k < ns; ++k) {
+      if (!L.terminal[k] && first[k + 1] == first[k]) L.terminal[k] = 1;  // all rows isolated
+      cont = cont || !L.terminal[k];
+    }
+    if (!cont) break;
     if (l == 0) candidate0();
     build_members(l);
     lev.emplace_back(new Level());
@@ -398,24 +539,26 @@ void Solver::setup() {
     if (mixed()) L.p32.alloc(L.n);
     launch_fill(L.n, 0.0, L.p.p, st);
     C.B.alloc(L.n_agg);
-    launch_normalize(L.n_agg, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.p.p, mixed() ? L.p32.p : nullptr,
-                     C.B.p, st);
+    launch_normalize(L.n_agg, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.p.p, nullptr, C.B.p, st);
     if (mixed()) launch_d2f(L.n, L.p.p, L.p32.p, nullptr, st);
     galerkin_symbolic(l);
     galerkin_numeric(l);
     L.has_next = true;
-    if ((double)L.n_agg > 0.95 * (double)L.n) force_last = stalled = true;
+    C.seg.assign(1, 0);
+    C.body.clear();
+    for (int k = 0; k < ns; ++k) {
+      if (L.terminal[k]) continue;
+      const int64_t na_k = first[k + 1] - first[k];
+      const int64_t nk = L.seg[k + 1] - L.seg[k];
+      C.seg.push_back(C.seg.back() + na_k);
+      C.body.push_back(L.body[k]);
+      if ((double)na_k > 0.95 * (double)nk) force_last[L.body[k]] = stalled[L.body[k]] = 1;
+    }
   }
   Level &last = *lev[nlev - 1];
-  if (last.n <= opt.dense_max) {
-    last_dense = true;
-    factor_last();
-  } else if (!stalled) {
-    last_dense = false;  // every row isolated or the level cap: smoothing only
-  } else {
-    throw Error(MGPBD_E_SETUP, "coarsening stalled with " + std::to_string(last.n) +
-                                   " rows above dense_max");
-  }
+  last.terminal.assign(last.seg.size() - 1, 1);
+  plan_dense();
+  factor_dense();
   ensure_vectors();
   built = true;
 }
@@ -428,17 +571,21 @@ void Solver::refresh() {
   reset_flags();
   for (int l = 0; l < nlev; ++l) {
     Level &L = *lev[l];
-    launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p,
-                        mixed() ? L.dinv32.p : nullptr, flags.p + kFBadDiag, st);
+    launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, nullptr,
+                        flags.p + kFBadDiag, st);
+    launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p,
+                   mixed() ? L.wdinv32.p : nullptr, st);
   }
   MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN, "non-positive diagonal entry");
-  if (last_dense) factor_last();
+  factor_dense();
 }
 
 void Solver::ensure_vectors() {
   const int64_t n = lev[0]->n;
   x.reserve(n); r.reserve(n); z.reserve(n); p.reserve(n); q.reserve(n);
-  if (opt.precision == MGPBD_PREC_MIXED) zold.reserve(n);
+  if (mixed()) zold.reserve(n);
+  ctl.reserve(nb);
+  ensure_pinned(std::max<size_t>(4096, sizeof(PcgCtl) * (size_t)nb + 64));
 }
 
 // ------------------------------------------------------------ V-cycle
@@ -449,7 +596,7 @@ template <> struct Buf<double> {
   static DevBuf<double> &r(Level &L) { return L.r; }
   static DevBuf<double> &res(Level &L) { return L.res; }
   static CsrView<double> A(const Level &L) { return L.view(); }
-  static const double *dinv(const Level &L) { return L.dinv.p; }
+  static const double *wdinv(const Level &L) { return L.wdinv.p; }
   static const double *p(const Level &L) { return L.p.p; }
 };
 template <> struct Buf<float> {
@@ -458,28 +605,39 @@ template <> struct Buf<float> {
   static DevBuf<float> &r(Level &L) { return L.r32; }
   static DevBuf<float> &res(Level &L) { return L.res32; }
   static CsrView<float> A(const Level &L) { return L.view32(); }
-  static const float *dinv(const Level &L) { return L.dinv32.p; }
+  static const float *wdinv(const Level &L) { return L.wdinv32.p; }
   static const float *p(const Level &L) { return L.p32.p; }
 };
 
-// `sweeps` omega-Jacobi sweeps; from_zero: the iterate starts at 0 (the
-// first sweep is z = omega D^-1 r, the first two are fused in one pass)
+template <>
+const MfView<double> *Solver::level_mf<double>(int l) const {
+  return (l == 0 && mf.ok()) ? &mf : nullptr;
+}
+template <>
+const MfView<float> *Solver::level_mf<float>(int l) const {
+  return (l == 0 && mf32.ok()) ? &mf32 : nullptr;
+}
+
+// `sweeps` weighted Jacobi sweeps; from_zero: the iterate starts at 0 and the
+// first sweep is z = omega D^-1 r
 template <class T>
-void Solver::smooth(Level &L, const T *r, T *&a, T *&b, int sweeps, bool from_zero) {
+void Solver::smooth(int l, const T *r, T *&a, T *&b, int sweeps, bool from_zero) {
+  Level &L = *lev[l];
   const int *done = done_ptr();
   CsrView<T> A = Buf<T>::A(L);
-  const T *dinv = Buf<T>::dinv(L);
-  const T om = (T)L.omega;
+  const MfView<T> *M = level_mf<T>(l);
+  const T *wd = Buf<T>::wdinv(L);
   int k = 0;
   if (from_zero) {
     // the first sweep from z = 0 is elementwise; fusing it into the second
     // would gather both r and D^-1 per entry, which costs more than the extra
     // pass over three vectors
-    if (sweeps >= 1) { launch_jacobi_first<T>(L.n, dinv, r, om, a, done, st); k = 1; }
+    if (sweeps >= 1) { launch_jacobi_first<T>(L.n, wd, r, a, done, st); k = 1; }
     else { launch_zero_t<T>(L.n, a, done, st); }
   }
   for (; k < sweeps; ++k) {
-    launch_jacobi<T>(A, dinv, r, om, a, b, done, st);
+    if (M) launch_mf_jacobi<T>(*M, wd, r, a, b, done, st);
+    else launch_jacobi<T>(A, wd, r, a, b, done, st);
     std::swap(a, b);
   }
 }
@@ -488,36 +646,31 @@ template <class T>
 void Solver::vcycle(int l, const T *r, T *z) {
   Level &L = *lev[l];
   const int *done = done_ptr();
-  if (l == nlev - 1 && last_dense) {
-    launch_dense_apply<T>(L.n, Ainv.p, r, z, done, st);
+  if (!L.smooth_here) {   // every body on this level ends with a dense solve
+    launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
+                                Ainv.p, r, z, done, st);
     return;
   }
   // start in the buffer that makes the last sweep land in z
   const int swaps = (opt.pre_sweeps > 0 ? opt.pre_sweeps - 1 : 0) + opt.post_sweeps;
   T *a = z, *b = Buf<T>::t(L).p;
   if (swaps % 2) std::swap(a, b);
-  smooth<T>(L, r, a, b, opt.pre_sweeps, true);
+  smooth<T>(l, r, a, b, opt.pre_sweeps, true);
   if (l + 1 < nlev) {
     Level &C = *lev[l + 1];
     T *res = Buf<T>::res(L).p;
-    launch_residual<T>(Buf<T>::A(L), r, a, res, done, st);
+    if (const MfView<T> *M = level_mf<T>(l)) launch_mf_residual<T>(*M, r, a, res, done, st);
+    else launch_residual<T>(Buf<T>::A(L), r, a, res, done, st);
     launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, Buf<T>::r(C).p, done, st);
     vcycle<T>(l + 1, Buf<T>::r(C).p, Buf<T>::z(C).p);
     launch_prolong<T>(L.n, L.agg.p, Buf<T>::p(L), Buf<T>::z(C).p, a, done, st);
   }
-  smooth<T>(L, r, a, b, opt.post_sweeps, false);
+  smooth<T>(l, r, a, b, opt.post_sweeps, false);
   if (a != z) launch_copy_t<T>(L.n, a, z, done, st);
-}
-
-void Solver::apply_vcycle(const double *rin, double *zout) {
-  if (mixed()) {
-    Level &F = *lev[0];
-    launch_d2f(F.n, rin, F.r32.p, done_ptr(), st);
-    vcycle<float>(0, F.r32.p, F.z32.p);
-    launch_f2d(F.n, F.z32.p, zout, done_ptr(), st);
-  } else {
-    vcycle<double>(0, rin, zout);
-  }
+  // bodies that end here with a dense solve: their rows are that solve's
+  if (!L.jobs.empty())
+    launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
+                                Ainv.p, r, z, done, st);
 }
 
 // ------------------------------------------------------------ PCG
@@ -525,38 +678,57 @@ void Solver::iterate_once(int k) {
   Level &F = *lev[0];
   const int64_t n = F.n;
   const bool flex = mixed();
+  SegTab t = F.tab.view();
   if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k], st));
-  launch_pcg_spmv_dot(ctl.p, F.view(), p.p, q.p, rb(), st);
+  if (nb == 1) {   // q = A p fused with the partial sums of p^T q
+    if (mf.ok()) launch_mf_pcg_spmv_dot(ctl.p, mf, p.p, q.p, partials(), st);
+    else launch_pcg_spmv_dot(ctl.p, F.view(), p.p, q.p, RedBuf{partials(), nullptr}, st);
+  } else {
+    if (mf.ok()) launch_mf_spmv<double>(mf, p.p, q.p, done_ptr(), st);
+    else launch_spmv<double>(F.view(), p.p, q.p, st);
+  }
   if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k + 1], st));
-  launch_pcg_update(ctl.p, n, p.p, q.p, x.p, r.p, rb(), st);
+  if (nb > 1) launch_s_pcg_dot_pq(t, ctl.p, p.p, q.p, partials(), st);
+  launch_s_pcg_update(t, ctl.p, p.p, q.p, x.p, r.p, partials(), all_done.p, st);
   if (flex) {
     launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
     vcycle<float>(0, F.r32.p, F.z32.p);
-    launch_pcg_rz(ctl.p, n, r.p, z.p, F.z32.p, zold.p, true, rb(), st);
+    launch_s_pcg_rz(t, ctl.p, r.p, z.p, F.z32.p, zold.p, true, partials(), all_done.p, st);
   } else {
     vcycle<double>(0, r.p, z.p);
-    launch_pcg_rz(ctl.p, n, r.p, z.p, nullptr, zold.p, false, rb(), st);
+    launch_s_pcg_rz(t, ctl.p, r.p, z.p, nullptr, zold.p, false, partials(), all_done.p, st);
   }
-  launch_pcg_pupdate(ctl.p, n, z.p, p.p, st);
+  launch_s_pcg_pupdate(t, ctl.p, z.p, p.p, st);
 }
 
-PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters, int force) {
+std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
+                                   const int32_t *force) {
   MG_REQUIRE(built, MGPBD_E_STATE, "solve without a hierarchy");
   Level &F = *lev[0];
   const int64_t n = F.n;
   ensure_vectors();
-  PcgCtl h{};
-  h.done = 0;
-  h.iters = 0;
-  h.force = force;
-  h.max_iters = max_iters;
-  h.tol = tol;
+  SegTab t = F.tab.view();
+  ensure_partials(t.nblk);
   PcgCtl *hp = static_cast<PcgCtl *>(pinned);
-  *hp = h;
-  MG_HIP(hipMemcpyAsync(ctl.p, hp, sizeof(PcgCtl), hipMemcpyHostToDevice, st));
-  launch_pcg_init(ctl.p, n, b, x.p, r.p, rb(), st);
-  apply_vcycle(r.p, z.p);
-  launch_pcg_init_p(ctl.p, n, r.p, z.p, p.p, zold.p, mixed(), rb(), st);
+  for (int k = 0; k < nb; ++k) {
+    PcgCtl h{};
+    h.done = 0;
+    h.iters = 0;
+    h.force = force ? force[k] : 0;
+    h.max_iters = max_iters;
+    h.tol = tol;
+    hp[k] = h;
+  }
+  MG_HIP(hipMemcpyAsync(ctl.p, hp, sizeof(PcgCtl) * nb, hipMemcpyHostToDevice, st));
+  launch_s_pcg_init(t, ctl.p, b, x.p, r.p, partials(), all_done.p, st);
+  if (mixed()) {
+    launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
+    vcycle<float>(0, F.r32.p, F.z32.p);
+    launch_f2d(n, F.z32.p, z.p, done_ptr(), st);
+  } else {
+    vcycle<double>(0, r.p, z.p);
+  }
+  launch_s_pcg_init_p(t, ctl.p, r.p, z.p, p.p, zold.p, mixed(), partials(), all_done.p, st);
   const int chunk = std::max(1, opt.check_every);
   // events around the fine-level product are recorded on the stream, so the
   // profiled solve launches kernels directly instead of replaying the graph
@@ -582,13 +754,20 @@ PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
     MG_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     graph_ok = true;
   }
+  auto max_iters_done = [&]() {
+    int m = 0;
+    for (int k = 0; k < nb; ++k) m = std::max(m, hp[k].iters + (hp[k].done == 2 ? 1 : 0));
+    return m;
+  };
   int launched = 0;
   while (true) {
-    // the control block tells whether the solve already ended
-    MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl), hipMemcpyDeviceToHost, st));
+    // the control blocks tell whether every solve already ended
+    MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl) * nb, hipMemcpyDeviceToHost, st));
     MG_HIP(hipStreamSynchronize(st));
-    if (hp->done || launched >= max_iters) break;
-    int before = hp->iters;
+    bool ended = true;
+    for (int k = 0; k < nb; ++k) ended = ended && hp[k].done != 0;
+    if (ended || launched >= max_iters) break;
+    const int before = max_iters_done();
     if (use_graph) {
       MG_HIP(hipGraphLaunch(gexec, st));
     } else {
@@ -596,9 +775,9 @@ PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
     }
     launched += chunk;
     if (opt.profile_spmv) {
-      MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl), hipMemcpyDeviceToHost, st));
+      MG_HIP(hipMemcpyAsync(hp, ctl.p, sizeof(PcgCtl) * nb, hipMemcpyDeviceToHost, st));
       MG_HIP(hipStreamSynchronize(st));
-      int ran = std::min(chunk, hp->iters - before + (hp->done == 2 ? 1 : 0));
+      const int ran = std::min(chunk, max_iters_done() - before);
       for (int k = 0; k < ran; ++k) {
         float ms = 0.f;
         MG_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
@@ -608,12 +787,13 @@ PcgResult Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
     }
   }
   if (x_out != x.p) launch_copy(n, x.p, x_out, nullptr, st);
-  PcgResult res;
-  res.status = hp->done;
-  res.iters = hp->iters;
-  res.ratio = hp->ratio;
-  res.bnorm = hp->bnorm;
-  if (res.status == 0) res.status = 4;
+  std::vector<PcgResult> res(nb);
+  for (int k = 0; k < nb; ++k) {
+    res[k].status = hp[k].done ? hp[k].done : 4;
+    res[k].iters = hp[k].iters;
+    res[k].ratio = hp[k].ratio;
+    res[k].bnorm = hp[k].bnorm;
+  }
   return res;
 }
 

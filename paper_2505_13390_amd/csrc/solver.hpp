@@ -1,9 +1,16 @@
 // AMG hierarchy (setup phase, Sec. 4.1-4.3, 4.5) and MGPCG solve (Sec. 4.4)
-// on one GPU. The host sequences kernels; all data stays in device memory.
+// on one GPU, for one body or for several bodies at once. Several bodies form
+// a block-diagonal system: every level stores the rows of the bodies that
+// reach it back to back (segments), each body keeps its own Jacobi weights,
+// coarsening depth, coarsest factor and PCG scalars, and every kernel of an
+// iteration covers all bodies in one launch. The host sequences kernels; all
+// data stays in device memory.
 #pragma once
 
 #include <memory>
 
+#include "mfree.hpp"
+#include "seg.hpp"
 #include "setup.hpp"
 
 namespace mgpbd {
@@ -16,14 +23,26 @@ struct Level {
   bool nt = false, nt32 = false;  // non-temporal matrix loads in the stream kernels
   DevBuf<int64_t> tiles, tiles32;
   int64_t ntiles = 0, ntiles32 = 0;
-  double omega = 0.0;
   DevBuf<int64_t> rowptr;
   DevBuf<int32_t> col;
   DevBuf<double> val;
   DevBuf<float> val32;
   DevBuf<int64_t> diagpos;
-  DevBuf<double> diag, dinv;
-  DevBuf<float> dinv32;
+  DevBuf<double> diag, dinv, wdinv;   // wdinv = omega(body) / a_ii
+  DevBuf<float> wdinv32;
+  // bodies present on this level
+  std::vector<int64_t> seg;           // row offsets, one segment per body
+  std::vector<int32_t> body;          // body id of each segment
+  std::vector<double> omega;          // Jacobi weight of each segment
+  std::vector<char> terminal;         // the body has no coarser level
+  SegTable tab;
+  DevBuf<double> d_omega;
+  // dense coarsest solves of the bodies that end here
+  std::vector<DenseJob> jobs;
+  DevBuf<DenseJob> d_jobs;
+  DevBuf<int64_t> d_jobstart;
+  int64_t job_rows = 0;
+  bool smooth_here = true;            // false when every body ending here is solved densely
   // entries of this (coarse) level: row of each entry and its transpose position
   DevBuf<int32_t> crow, mirror;
   // transfer to the next level
@@ -75,10 +94,15 @@ class Solver {
   hipStream_t st = nullptr;
   std::vector<std::unique_ptr<Level>> lev;
   int nlev = 0;
-  bool last_dense = false;
+  int nb = 1;                   // bodies (segments of level 0)
   bool built = false;
   bool val32_external = false;  // level-0 FP32 values written by the assembler
-  bool pattern_dirty = true;    // level-0 pattern changed: recompute diagpos/lanes
+  bool pattern_dirty = true;    // level-0 pattern changed: recompute diagpos / tuning
+
+  // matrix-free level-0 operator, set by a simulation context (unset: the
+  // level-0 passes read the assembled CSR); mf32 serves the FP32 V-cycle
+  MfView<double> mf;
+  MfView<float> mf32;
 
   // per-iteration profiling of the fine-level A p product
   int64_t spmv_calls = 0;
@@ -88,26 +112,28 @@ class Solver {
   bool mixed() const { return opt.precision == MGPBD_PREC_MIXED; }
   void set_stream(hipStream_t s);
   void invalidate_graph();
+  // row offsets of the bodies on level 0 (default: one body covering all rows)
+  void set_bodies(const std::vector<int64_t> &offsets);
+  // levels of body k in the current hierarchy
+  int body_levels(int k) const;
 
   // Full setup on the current level-0 values (aggregation, candidates, P,
-  // Galerkin pattern and values, omega, coarsest inverse).
+  // Galerkin pattern and values, omega, coarsest inverses).
   void setup();
   // Solving-phase refresh for new level-0 values with the kept P and omega.
   void refresh();
-  // MGPCG on A_0: x_out (device, may be the internal iterate) <- A_0^-1 b
-  PcgResult pcg(const double *b, double *x_out, double tol, int max_iters, int force);
-  // one preconditioner application z = V(r) (FP64 interface)
-  void apply_vcycle(const double *r, double *z);
-
+  // MGPCG on A_0 for every body at once: x_out <- A_0^-1 b; force (nullable,
+  // [nb]) fixes iteration counts. One result per body.
+  std::vector<PcgResult> pcg(const double *b, double *x_out, double tol, int max_iters,
+                             const int32_t *force);
   double *dl() { return x.p; }   // internal PCG iterate
-  // sum of squares of a device vector (deterministic), synchronous
-  double norm2(const double *v, int64_t n);
+  // per-body sum of squares of a level-0 vector (synchronous)
+  std::vector<double> norm2(const double *v);
 
  private:
-  // device scratch
   DevBuf<PcgCtl> ctl;
+  DevBuf<int> all_done;
   DevBuf<double> red_partials;
-  DevBuf<unsigned> red_ticket;
   DevBuf<double> x, r, z, p, q, zold;
   DevBuf<double> dscal;
   DevBuf<int> flags;
@@ -117,33 +143,36 @@ class Solver {
   DevBuf<uint64_t> key, m1;
   DevBuf<int32_t> itmp, itmp2;
   DevBuf<int64_t> ltmp, ltmp2;
-  DevBuf<double> dense, dscratch, Ainv;
-  int64_t nd = 0;
-  // pinned host staging
+  DevBuf<double> dscratch, Ainv;
+  std::vector<char> force_last, stalled;
   void *pinned = nullptr;
-  // graph of check_every PCG iterations
+  size_t pinned_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   std::vector<hipEvent_t> ev;
 
-  RedBuf rb() { return RedBuf{red_partials.p, red_ticket.p}; }
+  double *partials() { return red_partials.p; }
   const int *done_ptr() const;
   int read_flag(int k);
   void reset_flags();
   void ensure_vectors();
+  void ensure_pinned(size_t bytes);
+  void ensure_partials(int nblk);
   void finish_level(int l);
-  void aggregate(int l);
+  std::vector<int64_t> aggregate(int l);
   void candidate0();
   void build_members(int l);
   void galerkin_symbolic(int l);
   void galerkin_numeric(int l);
   void power_omega(int l);
   void tune_lanes(int l);
-  void factor_last();
+  void plan_dense();
+  void factor_dense();
   void iterate_once(int k);
   template <class T> void vcycle(int l, const T *r, T *z);
-  template <class T> void smooth(Level &L, const T *r, T *&a, T *&b, int sweeps, bool from_zero);
+  template <class T> void smooth(int l, const T *r, T *&a, T *&b, int sweeps, bool from_zero);
+  template <class T> const MfView<T> *level_mf(int l) const;
 };
 
 }  // namespace mgpbd

@@ -8,9 +8,9 @@ namespace mgpbd {
 
 void launch_predict(int64_t nv, const double *w, const double *g, double dt, double *const *xyz,
                     double *const *vxyz, double *const *oxyz, hipStream_t s);
-void launch_constraints(int64_t m, int64_t n_edges, const int32_t *rv, const double *rest_c,
+void launch_constraints(int64_t m, const int32_t *rv, const double *rest_c,
                         const double *const *xyz, double *C, double *grad, hipStream_t s);
-void launch_assemble(int64_t m, int64_t n_edges, int lanes, const int64_t *rp, const int32_t *col,
+void launch_assemble(int64_t m, int lanes, const int64_t *rp, const int32_t *col,
                      const uint32_t *meta, const int32_t *rv, const double *w, const double *grad,
                      const double *alpha_t, const double *C, const double *lambda, double *val,
                      float *val32, double *b, hipStream_t s);
@@ -20,6 +20,9 @@ void launch_dx_update(int64_t nv, const int64_t *vptr, const int32_t *vrow, cons
 void launch_lambda_add(int64_t m, double *lambda, const double *dl, hipStream_t s);
 void launch_velocity(int64_t nv, double dt, double *const *xyz, double *const *oxyz,
                      double *const *vxyz, hipStream_t s);
+// out = in + add (int32: negative entries kept as they are)
+void launch_offset_copy(int64_t n, const int32_t *in, int32_t add, int32_t *out, hipStream_t s);
+void launch_offset_copy(int64_t n, const int64_t *in, int64_t add, int64_t *out, hipStream_t s);
 void launch_check_finite(int64_t n, const double *a, int *bad, hipStream_t s);
 void launch_sqrt_div(int64_t n, const double *a, const double *b, double *s, double *q,
                      hipStream_t st);

@@ -20,9 +20,10 @@ def log(*a):
 
 def opts(**kw):
     """Matching (oracle, gpu) options; gpu-only keys: precision, use_graph,
-    check_every, profile_spmv."""
+    check_every, profile_spmv, spmv_tile, spmv_lanes, matrix_free."""
     gkw = {k: kw.pop(k) for k in list(kw) if k in ("precision", "use_graph", "check_every",
-                                                   "profile_spmv", "spmv_tile", "spmv_lanes")}
+                                                   "profile_spmv", "spmv_tile", "spmv_lanes",
+                                                   "matrix_free")}
     o = O.default_opts(**kw)
     if gkw.get("precision", 0) == B.PREC_MIXED:
         o.flexible = 1

@@ -46,6 +46,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.reuse_interval == 20 and o.precision == 0 and o.lmax_scale == 1.05
     assert o.use_graph == 1 and o.check_every == 8 and o.profile_spmv == 0
     assert o.spmv_tile == 0 and o.spmv_lanes == 0
+    assert o.matrix_free == 1
 
 
 def test_null_arguments_rejected_without_device_work():

@@ -133,16 +133,19 @@ def test_c0_first_iteration_assembly_and_setup_bit_exact():
     assert err <= 1e-9
 
 
-def test_c0_frame_positions_within_1e9():
+@pytest.mark.parametrize("mf", [1, 0])
+def test_c0_frame_positions_within_1e9(mf):
+    """Fine-level products matrix-free (default) or from the assembled CSR."""
     w = W.beam_c0()
-    sim, body, pos, vel, ores, gres = run_both(w, 20)
+    sim, body, pos, vel, ores, gres = run_both(w, 20, matrix_free=mf)
     log("oracle iters", ores[0]["pcg_iters"].tolist())
     log("gpu    iters", gres[0]["pcg_iters"].tolist())
     err = rel_pos_err(body.positions(), pos)
     verr = float(np.abs(body.velocities() - vel).max() / max(np.abs(vel).max(), 1e-300))
     lerr = float(np.abs(B.mgpbd_get_lambda(body.ctx, sim.m) - sim.lam()).max()
                  / np.abs(sim.lam()).max())
-    log("C0 frame: position err %.3e velocity err %.3e lambda err %.3e" % (err, verr, lerr))
+    log("C0 frame (matrix_free=%d): position err %.3e velocity err %.3e lambda err %.3e"
+        % (mf, err, verr, lerr))
     assert err <= 1e-9
     assert (gres[0]["pcg_ratio"] <= 1e-6).all()
 
@@ -162,7 +165,8 @@ def test_csr_pass_variants_match_oracle(tile, lanes):
     """Every CSR product variant the autotuner may pick (LDS stream tiles and
     lanes-per-row counts) gives oracle parity on the 8x8x32 beam."""
     w = W.beam_c0()
-    sim, body, pos, vel, ores, gres = run_both(w, 3, spmv_tile=tile, spmv_lanes=lanes)
+    sim, body, pos, vel, ores, gres = run_both(w, 3, spmv_tile=tile, spmv_lanes=lanes,
+                                               matrix_free=0)
     compare_hierarchy(sim, body, "tile %d lanes %d" % (tile, lanes), exact=False)
     err = rel_pos_err(body.positions(), pos)
     log("  position error %.3e iters %s %s" % (err, ores[0]["pcg_iters"].tolist(),
@@ -242,9 +246,10 @@ def test_solve_entry_matches_oracle():
     B.mgpbd_destroy(ctx)
 
 
-def test_mixed_precision_against_fp64_oracle():
+@pytest.mark.parametrize("mf", [1, 0])
+def test_mixed_precision_against_fp64_oracle(mf):
     w = W.beam_c0()
-    oo, go = opts(precision=B.PREC_MIXED)
+    oo, go = opts(precision=B.PREC_MIXED, matrix_free=mf)
     oo64, _ = opts()
     sim = O.Sim(w, oo64)
     pos, vel = O.positions(w)
