@@ -33,15 +33,44 @@ def spmv_bytes(m: int, nnz: int) -> int:
     return 12 * nnz + 8 * (m + 1) + 8 * m + 8 * m
 
 
-def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int) -> int:
-    """Algorithmic bytes of one matrix-free fine-level A p product: the vertex
-    gather reads the incidence pointers, rows and gradients, the inverse
-    masses and p, and writes u (4 doubles per vertex); the row pass reads the
-    row vertex ids, the gradient planes (3 doubles per edge row, 9 per volume
-    row), alpha~, p and u, and writes q."""
+def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int):
+    """Algorithmic bytes of the two kernels of one matrix-free fine-level A p
+    product. The vertex gather reads the incidence pointers, rows and
+    gradients, the inverse masses and p, and writes u (4 doubles per vertex);
+    the row pass reads the row vertex ids, the gradient planes (3 doubles per
+    edge row, 9 per volume row), alpha~, p and u, and writes q."""
     gather = 8 * (nv + 1) + 4 * n_inc + 24 * n_inc + 8 * nv + 8 * m + 32 * nv
     rows = 16 * m + 24 * n_edges + 72 * n_vols + 8 * m + 8 * m + 32 * nv + 8 * m
-    return gather + rows
+    return gather, rows
+
+
+def measured_traffic(name: str, sources):
+    """HBM bytes per launch from a committed counter summary (profiles/), or
+    None when the kernel sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("sources_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+MF_SOURCES = ("paper_2505_13390_amd/csrc/k_mfree.hip", "paper_2505_13390_amd/csrc/mfree.hpp",
+              "paper_2505_13390_amd/csrc/rowops.hpp")
 
 
 def cpu_baseline(w, seconds_hint: float = 20.0):
@@ -60,7 +89,7 @@ def cpu_baseline(w, seconds_hint: float = 20.0):
     val, b = sim.assemble(pos)
     rp, col = sim.pattern()
     h = O.Hier.build(rp, col, val)
-    iters = 10
+    iters = 50   # about 10-15 s of single-core work on the 32x32x128 beam
     t0 = time.perf_counter()
     _, st = h.pcg(b, 1e-6, 1000, force_iters=iters)
     dt = time.perf_counter() - t0
@@ -138,20 +167,32 @@ def main():
     roof = None
     if spmv_calls:
         avg_ms = spmv_ms / spmv_calls
+        first_ms = sum(r["spmv_first_ms"] for r in res) / spmv_calls
+        traffic = None
         if args.fine == "mf":
             ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
-            nbytes = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol, ne, nvol)
-            kname = ("k_mf_gather + k_mf_rows<OpPcgDot> (matrix-free fine-level A p with "
-                     "p^T A p)")
+            gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol, ne, nvol)
+            nbytes = gb + rb
+            kname = ("fine-level A p, matrix-free: k_mf_gather + k_mf_rows<OpPcgDot> "
+                     "(one launch each)")
+            parts = {"k_mf_gather": {"bytes": gb, "avg_ms": round(first_ms, 5),
+                                     "GB/s": round(gb / (first_ms * 1e-3) / 1e9, 1)},
+                     "k_mf_rows<OpPcgDot>": {"bytes": rb, "avg_ms": round(avg_ms - first_ms, 5),
+                                             "GB/s": round(rb / ((avg_ms - first_ms) * 1e-3)
+                                                           / 1e9, 1)}}
+            if args.config == "C1" and prec == B.PREC_FP64:
+                traffic = measured_traffic("k_mf_apply_beam32x32x128_counters.txt", MF_SOURCES)
         else:
             nbytes = spmv_bytes(body.m, body.nnz)
-            kname = "k_rows/k_stream<OpPcgDot> (CSR fine-level A p with p^T A p)"
+            kname = "fine-level A p, CSR: k_rows/k_stream<OpPcgDot>"
+            parts = None
         ach = nbytes / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": kname,
-                "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": kname, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
                 "launches": int(spmv_calls)}
+        if parts:
+            roof["parts"] = parts
     out = {
         "metric": METRIC, "value": value, "unit": "constraint-DOF*iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_frame,

@@ -134,7 +134,10 @@ typedef struct {
   double ms_pcg;        /* time spent in the PCG loops (hipEvents) */
   double ms_total;      /* whole frame (hipEvents) */
   int64_t spmv_calls;   /* fine-level A p launches timed (profile_spmv) */
-  double spmv_ms;       /* their summed duration */
+  double spmv_ms;       /* their summed duration (both kernels when matrix-free, without
+                           the one-block dot finisher) */
+  double spmv_first_ms; /* summed duration of the first kernel alone (the matrix-free
+                           vertex gather; 0 for the CSR product) */
 } mgpbd_step_stats;
 
 typedef struct {

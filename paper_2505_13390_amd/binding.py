@@ -52,7 +52,7 @@ class StepStats(C.Structure):
     _fields_ = [("bnorm", C.c_void_p), ("pcg_iters", C.c_void_p), ("pcg_ratio", C.c_void_p),
                 ("setup_ran", C.c_void_p), ("iters_done", C.c_int32), ("ms_setup", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("spmv_calls", C.c_int64),
-                ("spmv_ms", C.c_double)]
+                ("spmv_ms", C.c_double), ("spmv_first_ms", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -210,7 +210,7 @@ def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
     ratio = np.zeros(n)
     setup = np.zeros(n, np.int32)
     st = StepStats(_np_ptr(bn).value, _np_ptr(its).value, _np_ptr(ratio).value,
-                   _np_ptr(setup).value, 0, 0.0, 0.0, 0.0, 0, 0.0)
+                   _np_ptr(setup).value, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
     _prepare(ctx)
     s = lib().mgpbd_step(ctx, _dev(x, f64), _dev(y, f64), _dev(z, f64), _dev(vx, f64),
                          _dev(vy, f64), _dev(vz, f64), int(n_iters),
@@ -219,7 +219,7 @@ def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
     k = st.iters_done
     return dict(bnorm=bn[:k], pcg_iters=its[:k], pcg_ratio=ratio[:k], setup_ran=setup[:k],
                 iters_done=k, ms_setup=st.ms_setup, ms_pcg=st.ms_pcg, ms_total=st.ms_total,
-                spmv_calls=st.spmv_calls, spmv_ms=st.spmv_ms)
+                spmv_calls=st.spmv_calls, spmv_ms=st.spmv_ms, spmv_first_ms=st.spmv_first_ms)
 
 
 def mgpbd_solve(ctx, rowptr, col, val, b, tol, x_out):
@@ -359,7 +359,7 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
     for k, a in enumerate(arrs):
         sts[k] = StepStats(_np_ptr(a["bnorm"]).value, _np_ptr(a["pcg_iters"]).value,
                            _np_ptr(a["pcg_ratio"]).value, _np_ptr(a["setup_ran"]).value,
-                           0, 0.0, 0.0, 0.0, 0, 0.0)
+                           0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
     sys_ctx = mgpbd_batch_context(batch)
     _prepare(sys_ctx)
     st = lib().mgpbd_batch_step(batch, xs, vs, int(n_iters), sts if stats else None)
@@ -371,7 +371,7 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
                         pcg_ratio=a["pcg_ratio"][:d], setup_ran=a["setup_ran"][:d],
                         iters_done=d, ms_setup=sts[k].ms_setup, ms_pcg=sts[k].ms_pcg,
                         ms_total=sts[k].ms_total, spmv_calls=sts[k].spmv_calls,
-                        spmv_ms=sts[k].spmv_ms))
+                        spmv_ms=sts[k].spmv_ms, spmv_first_ms=sts[k].spmv_first_ms))
     return out
 
 

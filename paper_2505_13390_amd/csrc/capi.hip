@@ -191,6 +191,7 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
   double ms_setup = 0.0, ms_pcg = 0.0;
   S.spmv_calls = 0;
   S.spmv_ms = 0.0;
+  S.spmv_first_ms = 0.0;
   launch_predict(nv, c->w.p, c->g, c->dt, xyz, vxyz, oxyz, st);
   launch_fill(m, 0.0, c->lambda.p, st);
   Level &F = S.L0();
@@ -267,6 +268,7 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
       stats[k].ms_total = ms_total;
       stats[k].spmv_calls = S.spmv_calls;
       stats[k].spmv_ms = S.spmv_ms;
+      stats[k].spmv_first_ms = S.spmv_first_ms;
     }
 }
 

@@ -152,6 +152,19 @@ void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, cons
   launch_mf_pass<T>(A, z, OpResidual<T>{r, res}, done, nullptr, s);
 }
 
+void launch_mf_gather(const MfView<double> &A, const double *x, const int *done, hipStream_t s) {
+  if (A.m && A.nv)
+    k_mf_gather<kMfLanes, double>
+        <<<grid_for(A.nv * kMfLanes, kBlock), kBlock, 0, s>>>(done, A, x);
+}
+int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, const int *done,
+                       double *partials, hipStream_t s) {
+  if (!A.m) return 0;
+  const int grid = grid_for(A.m, kBlock);
+  k_mf_rows<double, OpPcgDot><<<grid, kBlock, 0, s>>>(done, A, p, OpPcgDot{p, q}, partials);
+  return grid;
+}
+
 void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *p, double *q,
                             double *partials, hipStream_t s) {
   const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field

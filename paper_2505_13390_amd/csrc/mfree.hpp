@@ -46,5 +46,11 @@ void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, cons
 // q = A p and the PCG step length (one control block)
 void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *p, double *q,
                             double *partials, hipStream_t s);
+// the two kernels of that product on their own (for per-kernel timing):
+// the vertex gather, then the row pass writing q and the partial sums of
+// p^T q (returns the number of partials; launch_fin_pq finishes)
+void launch_mf_gather(const MfView<double> &A, const double *x, const int *done, hipStream_t s);
+int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, const int *done,
+                       double *partials, hipStream_t s);
 
 }  // namespace mgpbd

@@ -679,15 +679,35 @@ void Solver::iterate_once(int k) {
   const int64_t n = F.n;
   const bool flex = mixed();
   SegTab t = F.tab.view();
-  if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k], st));
+  // profiling: events before the product, after its first kernel (the
+  // matrix-free gather) and after its last kernel (before the dot finisher)
+  auto mark = [&](int j) {
+    if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[3 * k + j], st));
+  };
+  mark(0);
   if (nb == 1) {   // q = A p fused with the partial sums of p^T q
-    if (mf.ok()) launch_mf_pcg_spmv_dot(ctl.p, mf, p.p, q.p, partials(), st);
-    else launch_pcg_spmv_dot(ctl.p, F.view(), p.p, q.p, RedBuf{partials(), nullptr}, st);
+    int grid;
+    if (mf.ok()) {
+      launch_mf_gather(mf, p.p, done_ptr(), st);
+      mark(1);
+      grid = launch_mf_rows_dot(mf, p.p, q.p, done_ptr(), partials(), st);
+    } else {
+      mark(1);
+      grid = launch_spmv_dot_partials(F.view(), p.p, q.p, done_ptr(), partials(), st);
+    }
+    mark(2);
+    launch_fin_pq(ctl.p, partials(), grid, st);
   } else {
-    if (mf.ok()) launch_mf_spmv<double>(mf, p.p, q.p, done_ptr(), st);
-    else launch_spmv<double>(F.view(), p.p, q.p, st);
+    if (mf.ok()) {
+      launch_mf_gather(mf, p.p, done_ptr(), st);
+      mark(1);
+      launch_mf_rows_dot(mf, p.p, q.p, done_ptr(), nullptr, st);
+    } else {
+      mark(1);
+      launch_spmv<double>(F.view(), p.p, q.p, st);
+    }
+    mark(2);
   }
-  if (opt.profile_spmv) MG_HIP(hipEventRecord(ev[2 * k + 1], st));
   if (nb > 1) launch_s_pcg_dot_pq(t, ctl.p, p.p, q.p, partials(), st);
   launch_s_pcg_update(t, ctl.p, p.p, q.p, x.p, r.p, partials(), all_done.p, st);
   if (flex) {
@@ -733,10 +753,10 @@ std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, i
   // events around the fine-level product are recorded on the stream, so the
   // profiled solve launches kernels directly instead of replaying the graph
   const bool use_graph = opt.use_graph && !opt.profile_spmv && st != nullptr;
-  if (opt.profile_spmv && (int)ev.size() < 2 * chunk) {
+  if (opt.profile_spmv && (int)ev.size() < 3 * chunk) {
     invalidate_graph();
     for (auto e : ev) (void)hipEventDestroy(e);
-    ev.assign(2 * chunk, nullptr);
+    ev.assign(3 * chunk, nullptr);
     for (auto &e : ev) MG_HIP(hipEventCreate(&e));
   }
   if (use_graph && !graph_ok) {
@@ -779,9 +799,11 @@ std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, i
       MG_HIP(hipStreamSynchronize(st));
       const int ran = std::min(chunk, max_iters_done() - before);
       for (int k = 0; k < ran; ++k) {
-        float ms = 0.f;
-        MG_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        float ms = 0.f, ms1 = 0.f;
+        MG_HIP(hipEventElapsedTime(&ms, ev[3 * k], ev[3 * k + 2]));
+        MG_HIP(hipEventElapsedTime(&ms1, ev[3 * k], ev[3 * k + 1]));
         spmv_ms += ms;
+        spmv_first_ms += ms1;
         ++spmv_calls;
       }
     }

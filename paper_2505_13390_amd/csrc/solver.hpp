@@ -106,7 +106,8 @@ class Solver {
 
   // per-iteration profiling of the fine-level A p product
   int64_t spmv_calls = 0;
-  double spmv_ms = 0.0;
+  double spmv_ms = 0.0;        // whole product (both kernels when matrix-free)
+  double spmv_first_ms = 0.0;  // its first kernel (the matrix-free gather; 0 for CSR)
 
   Level &L0() { return *lev[0]; }
   bool mixed() const { return opt.precision == MGPBD_PREC_MIXED; }
