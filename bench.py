@@ -100,13 +100,73 @@ def cpu_baseline(w, seconds_hint: float = 20.0):
                       % (w.name, st["iters"], dt)}
 
 
+def bench_batch(args, B, W):
+    """The 64 beams of the batch workload, stepped together as one
+    block-diagonal system (default) or one after another (--sequential)."""
+    import numpy as np
+    import torch
+    ws = W.batch_c3()
+    n_iters = args.iters or ws[0].iters
+    prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
+    opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
+                                  matrix_free=1 if args.fine == "mf" else 0)
+    if args.max_pcg:
+        opt.max_pcg = args.max_pcg
+    rows = [w.n_rows for w in ws]
+    t0 = time.perf_counter()
+    if args.sequential:
+        bodies = [B.Body(w, opt) for w in ws]
+        step = lambda: [b.step(n_iters) for b in bodies]
+    else:
+        batch = B.Batch(ws, opt)
+        step = lambda: batch.step(n_iters)
+    print("created %d bodies (%d rows) in %.1f s" % (len(ws), sum(rows), time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    for f in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for f in range(args.steps):
+        r = step()
+        res.append(r)
+        ms = sum(x["ms_total"] for x in r) if args.sequential else r[0]["ms_total"]
+        its = [int(x["pcg_iters"].sum()) for x in r]
+        print("frame %d: %.1f ms, pcg iterations per body (sum over the frame) min %d max %d"
+              % (args.warmup + f, ms, min(its), max(its)), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dof_iters = sum(float(m) * float(x["pcg_iters"].sum()) for r in res for m, x in zip(rows, r))
+    if args.sequential:
+        pcg_s = sum(x["ms_pcg"] for r in res for x in r) / 1e3
+    else:
+        pcg_s = sum(r[0]["ms_pcg"] for r in res) / 1e3
+    out = {
+        "metric": METRIC, "value": dof_iters / pcg_s, "unit": "constraint-DOF*iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == B.PREC_FP64 else "f32 V-cycle / f64 PCG", "data": "synthetic",
+        "config": {"workload": "batch_64_beams_n4-24", "bodies": len(ws), "rows": sum(rows),
+                   "mode": "sequential contexts" if args.sequential else "one batch",
+                   "iters_per_frame": n_iters, "precision": args.precision,
+                   "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
+                   "ms_pcg_per_frame": 1e3 * pcg_s / args.steps},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3"],
+                    help="C3: the 64-beam batch (a comparison run, not the headline line)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64, mixed for C3")
+    ap.add_argument("--sequential", action="store_true",
+                    help="C3: step the bodies one after another, each as its own context")
     ap.add_argument("--reuse", type=int, default=20)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--max-pcg", type=int, default=None)
@@ -131,6 +191,11 @@ def main():
     from paper_2505_13390_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.precision is None:
+        args.precision = "mixed" if args.config == "C3" else "fp64"
+    if args.config == "C3":
+        bench_batch(args, B, W)
+        return
     w = W.CONFIGS[args.config]()
     n_iters = args.iters or w.iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64

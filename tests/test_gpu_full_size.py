@@ -1,0 +1,112 @@
+"""Parity at the full size of the 32x32x128 beam (1,731,776 rows, 155,246,662
+entries), in the configuration bench.py times: the first global iteration of
+frame 0. Checked element by element where the oracle can compute the whole
+result (assembly of A and b, the complete AMG hierarchy of that A), and by
+properties that hold at any size elsewhere (true residual of the PCG solve,
+agreement of the matrix-free and assembled fine operators)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2505_13390_amd import workloads as W
+from tests.gpu_common import B, log, opts, rel_pos_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    w = W.beam_c1()
+    oo, go = opts()
+    body = B.Body(w, go)
+    res = body.step(1)
+    log("C1 GPU first iteration: pcg iters", res["pcg_iters"].tolist(),
+        "ratio %.3e" % res["pcg_ratio"][0])
+    yield w, oo, body, res
+    body.close()
+
+
+def predicted(w):
+    pos, vel = O.positions(w)
+    free = w.inv_mass > 0
+    vel[free] += w.dt * np.asarray(w.gravity)
+    pos[free] += w.dt * vel[free]
+    return pos
+
+
+def test_c1_assembly_bitwise(c1):
+    w, oo, body, _ = c1
+    sim = O.Sim(w, oo)
+    val, b = sim.assemble(predicted(w))
+    rp, col = sim.pattern()
+    grp, gcol, gval = B.mgpbd_get_matrix(body.ctx, 0)
+    assert np.array_equal(grp, rp) and np.array_equal(gcol, col)
+    nbad = int((gval.view(np.uint64) != val.view(np.uint64)).sum())
+    log("C1 assembly: %d of %d values differ" % (nbad, val.size))
+    assert nbad == 0
+    gb = B.mgpbd_get_rhs(body.ctx, sim.m)
+    assert np.array_equal(gb.view(np.uint64), b.view(np.uint64))
+
+
+def test_c1_hierarchy_bitwise(c1):
+    """The whole setup of the oracle on the same A (tens of seconds on one core)
+    against the GPU's: every level's pattern and values, aggregates, P and
+    candidates bit-identical, the level-0 colours identical."""
+    w, oo, body, _ = c1
+    grp, gcol, gval = B.mgpbd_get_matrix(body.ctx, 0)
+    h = O.Hier.build(grp, gcol, gval, oo)
+    L = B.mgpbd_num_levels(body.ctx)
+    log("C1 levels: oracle %d gpu %d" % (h.levels, L))
+    assert L == h.levels
+    for l in range(L):
+        gi = B.mgpbd_get_level(body.ctx, l)
+        oi = h.info(l)
+        log("  level %d: n %d nnz %d" % (l, gi["n"], gi["nnz"]))
+        assert gi["n"] == oi["n"] and gi["nnz"] == oi["nnz"]
+        if l > 0:
+            r, c, v = B.mgpbd_get_matrix(body.ctx, l)
+            orp, ocol, oval = h.matrix(l)
+            assert np.array_equal(r, orp) and np.array_equal(c, ocol)
+            assert np.array_equal(v.view(np.uint64), oval.view(np.uint64)), "level %d values" % l
+        if l + 1 < L:
+            gagg = B.mgpbd_get_aggregates(body.ctx, l)
+            oagg, op, oB = h.transfer(l)
+            assert np.array_equal(gagg, oagg), "level %d aggregates" % l
+            gp, gB = B.mgpbd_get_transfer(body.ctx, l)
+            assert np.array_equal(gp.view(np.uint64), op.view(np.uint64)), "level %d P" % l
+            assert np.array_equal(gB.view(np.uint64), oB.view(np.uint64)), "level %d B" % l
+    oc, onc = h.colors()
+    gc, gnc = B.mgpbd_get_colors(body.ctx, int(grp.size - 1))
+    assert gnc == onc and np.array_equal(gc, oc)
+
+
+def test_c1_true_residual(c1):
+    import scipy.sparse as sp
+    w, oo, body, res = c1
+    rp, col, val = B.mgpbd_get_matrix(body.ctx, 0)
+    A = sp.csr_matrix((val, col, rp))
+    m = rp.size - 1
+    b = B.mgpbd_get_rhs(body.ctx, m)
+    x = B.mgpbd_get_lambda(body.ctx, m)
+    rel = float(np.linalg.norm(A @ x - b) / np.linalg.norm(b))
+    log("C1 true relative residual %.3e (recurrence %.3e)" % (rel, res["pcg_ratio"][0]))
+    assert res["pcg_ratio"][0] <= 1e-6
+    assert rel <= 1.5e-6
+
+
+def test_c1_matrix_free_matches_assembled(c1):
+    w, oo, body, res = c1
+    _, go = opts(matrix_free=0)
+    csr = B.Body(w, go)
+    rc = csr.step(1)
+    err = rel_pos_err(body.positions(), csr.positions())
+    log("C1 matrix-free vs CSR: iters %d / %d, position difference %.3e"
+        % (res["pcg_iters"][0], rc["pcg_iters"][0], err))
+    csr.close()
+    assert abs(int(res["pcg_iters"][0]) - int(rc["pcg_iters"][0])) <= 0.05 * rc["pcg_iters"][0]
+    assert err <= 1e-9
