@@ -35,12 +35,12 @@ def spmv_bytes(m: int, nnz: int) -> int:
 
 def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int):
     """Algorithmic bytes of the two kernels of one matrix-free fine-level A p
-    product. The vertex gather reads the incidence pointers, rows and
-    gradients, the inverse masses and p, and writes u (4 doubles per vertex);
-    the row pass reads the row vertex ids, the gradient planes (3 doubles per
-    edge row, 9 per volume row), alpha~, p and u, and writes q."""
+    product (every array counted once). The vertex gather reads the incidence
+    pointers, rows and gradients, the inverse masses and p, and writes u (4
+    values per vertex); the row pass reads the row vertex ids, the positions
+    (its gradients are recomputed from them), u, alpha~ and p, and writes q."""
     gather = 8 * (nv + 1) + 4 * n_inc + 24 * n_inc + 8 * nv + 8 * m + 32 * nv
-    rows = 16 * m + 24 * n_edges + 72 * n_vols + 8 * m + 8 * m + 32 * nv + 8 * m
+    rows = 16 * m + 32 * nv + 32 * nv + 8 * m + 8 * m + 8 * m
     return gather, rows
 
 

@@ -44,10 +44,11 @@ struct mgpbd_ctx {
   DevBuf<int8_t> vslot;
   DevBuf<double> w, alpha_t, rest_c, C, grad, lambda, b, old[3];
   DevBuf<int> bad;
-  // matrix-free fine operator: gradient planes, per-incidence gradients,
-  // gather scratch (FP64; FP32 copies for the mixed V-cycle)
-  DevBuf<double> mf_gp, mf_gT, mf_u;
-  DevBuf<float> mf_gp32, mf_gT32, mf_u32, mf_alpha32, mf_w32;
+  // matrix-free fine operator: positions of the current iteration, the
+  // per-incidence gradients and the gather scratch (FP64; FP32 copies for the
+  // mixed V-cycle)
+  DevBuf<double> mf_pos, mf_gT, mf_u;
+  DevBuf<float> mf_pos32, mf_gT32, mf_u32, mf_alpha32, mf_w32;
   std::vector<int32_t> force;
   bool have_rhs = false;
   bool batch_owned = false;   // the system context of a batch (freed with it)
@@ -141,26 +142,28 @@ void alloc_state(mgpbd_ctx *c) {
   S.mf = MfView<double>();
   S.mf32 = MfView<float>();
   if (c->opt.matrix_free && c->m > 0) {
-    const int64_t n_inc = (int64_t)c->vrow.n;
-    c->mf_gp.alloc(12 * (size_t)c->m);
-    c->mf_gT.alloc(3 * (size_t)std::max<int64_t>(n_inc, 1));
-    c->mf_u.alloc(4 * (size_t)std::max<int64_t>(c->nv, 1));
+    const size_t nv4 = 4 * (size_t)std::max<int64_t>(c->nv, 1);
+    const size_t ninc3 = 3 * (size_t)std::max<int64_t>((int64_t)c->vrow.n, 1);
+    c->mf_pos.alloc(nv4);
+    c->mf_gT.alloc(ninc3);
+    c->mf_u.alloc(nv4);
     MfView<double> v;
-    v.m = c->m; v.nv = c->nv; v.rv = c->rv.p; v.gp = c->mf_gp.p; v.alpha = c->alpha_t.p;
-    v.vptr = c->vptr.p; v.vrow = c->vrow.p; v.gT = c->mf_gT.p; v.w = c->w.p; v.u = c->mf_u.p;
+    v.m = c->m; v.nv = c->nv; v.rv = c->rv.p; v.pos = c->mf_pos.p; v.alpha = c->alpha_t.p;
+    v.vptr = c->vptr.p; v.vrow = c->vrow.p; v.gT = c->mf_gT.p; v.w = c->w.p;
+    v.u = c->mf_u.p;
     S.mf = v;
     if (S.mixed()) {
-      c->mf_gp32.alloc(12 * (size_t)c->m);
-      c->mf_gT32.alloc(3 * (size_t)std::max<int64_t>(n_inc, 1));
-      c->mf_u32.alloc(4 * (size_t)std::max<int64_t>(c->nv, 1));
+      c->mf_pos32.alloc(nv4);
+      c->mf_gT32.alloc(ninc3);
+      c->mf_u32.alloc(nv4);
       c->mf_alpha32.alloc(c->m);
       c->mf_w32.alloc(std::max<int64_t>(c->nv, 1));
       launch_d2f(c->m, c->alpha_t.p, c->mf_alpha32.p, nullptr, c->st);
       launch_d2f(c->nv, c->w.p, c->mf_w32.p, nullptr, c->st);
       MfView<float> f;
-      f.m = c->m; f.nv = c->nv; f.rv = c->rv.p; f.gp = c->mf_gp32.p; f.alpha = c->mf_alpha32.p;
-      f.vptr = c->vptr.p; f.vrow = c->vrow.p; f.gT = c->mf_gT32.p; f.w = c->mf_w32.p;
-      f.u = c->mf_u32.p;
+      f.m = c->m; f.nv = c->nv; f.rv = c->rv.p; f.pos = c->mf_pos32.p;
+      f.alpha = c->mf_alpha32.p; f.vptr = c->vptr.p; f.vrow = c->vrow.p; f.gT = c->mf_gT32.p;
+      f.w = c->mf_w32.p; f.u = c->mf_u32.p;
       S.mf32 = f;
     }
   }
@@ -203,11 +206,11 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
     launch_constraints(m, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
     const int64_t n_inc = (int64_t)c->vrow.n;
     if (S.mf.ok())
-      launch_mf_prepare<double>(m, n_inc, c->rv.p, c->grad.p, c->vrow.p, c->vslot.p,
-                                c->mf_gp.p, c->mf_gT.p, st);
+      launch_mf_prepare<double>(nv, xyz[0], xyz[1], xyz[2], n_inc, c->vrow.p, c->vslot.p,
+                                c->grad.p, c->mf_pos.p, c->mf_gT.p, st);
     if (S.mf32.ok())
-      launch_mf_prepare<float>(m, n_inc, c->rv.p, c->grad.p, c->vrow.p, c->vslot.p,
-                               c->mf_gp32.p, c->mf_gT32.p, st);
+      launch_mf_prepare<float>(nv, xyz[0], xyz[1], xyz[2], n_inc, c->vrow.p, c->vslot.p,
+                               c->grad.p, c->mf_pos32.p, c->mf_gT32.p, st);
     launch_assemble(m, 16, F.rowptr.p, F.col.p, c->meta.p, c->rv.p, c->w.p, c->grad.p,
                     c->alpha_t.p, c->C.p, c->lambda.p, F.val.p, S.mixed() ? F.val32.p : nullptr,
                     c->b.p, st);

@@ -1,7 +1,8 @@
 // Matrix-free fine-level passes (see mfree.hpp): A x = J W J^T x + alpha~ x
-// (Eq. 3) from per-row gradient planes and per-incidence gradients. Each pass
-// is a vertex gather followed by a row pass that ends in the same epilogues
-// as the CSR passes (product, Jacobi sweep, residual, PCG product + dot).
+// (Eq. 3) with the gradients recomputed from the positions. Each pass is a
+// vertex gather followed by a row pass that ends in the same epilogues as the
+// CSR passes (product, Jacobi sweep, residual, PCG product + dot).
+#include "grad.hpp"
 #include "mfree.hpp"
 #include "rowops.hpp"
 
@@ -11,18 +12,15 @@ constexpr int kMfLanes = 8;   // lanes per vertex in the gather (about 36 rows p
 
 // ---------------------------------------------------------------- prepare
 template <class T>
-__global__ void k_mf_planes(int64_t m, const int32_t *__restrict__ rv,
-                            const double *__restrict__ grad, T *__restrict__ gp) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
-  const double *g = grad + 12 * c;
-  if (rv[4 * c + 2] < 0) {   // edge row: slot 1 is the negated slot 0
-#pragma unroll
-    for (int d = 0; d < 3; ++d) gp[d * m + c] = (T)g[d];
-  } else {                   // volume row: slot 0 is minus the sum of slots 1-3
-#pragma unroll
-    for (int q = 3; q < 12; ++q) gp[q * m + c] = (T)g[q];
-  }
+__global__ void k_mf_pos(int64_t nv, const double *__restrict__ x, const double *__restrict__ y,
+                         const double *__restrict__ z, T *__restrict__ pos) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  T *p = pos + 4 * v;
+  p[0] = (T)x[v];
+  p[1] = (T)y[v];
+  p[2] = (T)z[v];
+  p[3] = (T)0;
 }
 
 template <class T>
@@ -39,16 +37,17 @@ __global__ void k_mf_incidence(int64_t n_inc, const int32_t *__restrict__ vrow,
 }
 
 template <class T>
-void launch_mf_prepare(int64_t m, int64_t n_inc, const int32_t *rv, const double *grad,
-                       const int32_t *vrow, const int8_t *vslot, T *gp, T *gT, hipStream_t s) {
-  if (m) k_mf_planes<T><<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, rv, grad, gp);
+void launch_mf_prepare(int64_t nv, const double *x, const double *y, const double *z,
+                       int64_t n_inc, const int32_t *vrow, const int8_t *vslot,
+                       const double *grad, T *pos, T *gT, hipStream_t s) {
+  if (nv) k_mf_pos<T><<<blocks_for(nv, kBlock), kBlock, 0, s>>>(nv, x, y, z, pos);
   if (n_inc)
     k_mf_incidence<T><<<blocks_for(n_inc, kBlock), kBlock, 0, s>>>(n_inc, vrow, vslot, grad, gT);
 }
 
 // ----------------------------------------------------------------- passes
-// u_v = w_v sum_{e in incidence(v)} gT_e x_{row(e)}; G lanes per vertex with
-// a fixed lane assignment and a fixed-tree sum.
+// u_v = w_v sum_{e in incidence(v)} gT_e x_{row(e)}; G lanes per vertex with a
+// fixed lane assignment and a fixed-tree sum.
 template <int G, class T>
 __global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T> A,
                                                       const T *__restrict__ x) {
@@ -84,38 +83,55 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T>
   }
 }
 
-// (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c, one thread per row.
+template <class T>
+__device__ __forceinline__ T dot_u(const T (&g)[3], const T *__restrict__ u) {
+  return (g[0] * u[0] + g[1] * u[1]) + g[2] * u[2];
+}
+
+// (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c, one thread per row. The
+// slot gradients are formed one at a time (the same expressions as
+// tet_grads) and consumed at once, which keeps the register count low enough
+// for full occupancy.
 template <class T, class Op>
-__global__ __launch_bounds__(kBlock) void k_mf_rows(const int *done, MfView<T> A,
+__global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T> A,
                                                     const T *__restrict__ x, Op op,
                                                     double *partials) {
   if (done && *done) return;
   const int64_t m = A.m;
+  const T *__restrict__ pos = A.pos;
+  const T *__restrict__ u = A.u;
   int64_t lo, hi;
   block_range(m, lo, hi);
   double acc = 0.0;
   for (int64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
     const int4 r = *reinterpret_cast<const int4 *>(A.rv + 4 * c);
+    const int64_t va = r.x, vb = r.y;
     T s;
     if (r.z < 0) {
-      const T gx = A.gp[c], gy = A.gp[m + c], gz = A.gp[2 * m + c];
-      const T *ui = A.u + 4 * (int64_t)r.x, *uj = A.u + 4 * (int64_t)r.y;
-      s = (gx * (ui[0] - uj[0]) + gy * (ui[1] - uj[1])) + gz * (ui[2] - uj[2]);
+      T g0[3], g1[3];
+      edge_grads(pos + 4 * va, pos + 4 * vb, g0, g1);
+      s = dot_u(g0, u + 4 * va);
+      s += dot_u(g1, u + 4 * vb);
     } else {
-      T g[4][3];
+      const int64_t vc = r.z, vd = r.w;
+      T e1[3], e2[3], e3[3], cr[3], g1[3], g2[3], g3[3], g0[3];
+      tet_edges(pos + 4 * va, pos + 4 * vb, pos + 4 * vc, pos + 4 * vd, e1, e2, e3);
+      cross(e2, e3, cr);
 #pragma unroll
-      for (int k = 1; k < 4; ++k)
+      for (int d = 0; d < 3; ++d) g1[d] = cr[d] / (T)6;
+      cross(e3, e1, cr);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[k][d] = A.gp[(3 * k + d) * m + c];
+      for (int d = 0; d < 3; ++d) g2[d] = cr[d] / (T)6;
+      cross(e1, e2, cr);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) g[0][d] = -((g[1][d] + g[2][d]) + g[3][d]);
-      const int32_t vs[4] = {r.x, r.y, r.z, r.w};
-      s = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T *uk = A.u + 4 * (int64_t)vs[k];
-        s += (g[k][0] * uk[0] + g[k][1] * uk[1]) + g[k][2] * uk[2];
+      for (int d = 0; d < 3; ++d) {
+        g3[d] = cr[d] / (T)6;
+        g0[d] = -((g1[d] + g2[d]) + g3[d]);
       }
+      s = dot_u(g0, u + 4 * va);
+      s += dot_u(g1, u + 4 * vb);
+      s += dot_u(g2, u + 4 * vc);
+      s += dot_u(g3, u + 4 * vd);
     }
     s = s + A.alpha[c] * x[c];
     op(c, s, acc);
@@ -173,8 +189,9 @@ void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *
 }
 
 #define MG_INST(T)                                                                              \
-  template void launch_mf_prepare<T>(int64_t, int64_t, const int32_t *, const double *,        \
-                                     const int32_t *, const int8_t *, T *, T *, hipStream_t);   \
+  template void launch_mf_prepare<T>(int64_t, const double *, const double *, const double *,  \
+                                     int64_t, const int32_t *, const int8_t *, const double *,  \
+                                     T *, T *, hipStream_t);                                    \
   template void launch_mf_spmv<T>(const MfView<T> &, const T *, T *, const int *, hipStream_t); \
   template void launch_mf_jacobi<T>(const MfView<T> &, const T *, const T *, const T *, T *,    \
                                     const int *, hipStream_t);                                  \

@@ -4,6 +4,7 @@
 // pattern (Eq. 3, per-entry form of Sec. 4.2), dx = M^-1 gradC^T dlambda
 // (Eq. 5) gathered per vertex, lambda += dlambda, and the velocity update.
 // Positions and velocities are SoA FP64 arrays.
+#include "grad.hpp"
 #include "xpbd.hpp"
 
 namespace mgpbd {
@@ -31,9 +32,8 @@ void launch_predict(int64_t nv, const double *w, const double *g, double dt, dou
                                                         oxyz[1], oxyz[2]);
 }
 
-// C and gradient of each row. Edge (i, j): C = |x_i - x_j| - L0, g_i = n,
-// g_j = -n. Volume (a, b, c, d): V = e1.(e2 x e3)/6, C = V - V0,
-// g_b = (e2 x e3)/6, g_c = (e3 x e1)/6, g_d = (e1 x e2)/6, g_a = -(g_b + g_c + g_d).
+// C and gradient of each row (formulas in grad.hpp): edge C = |x_i - x_j| - L0,
+// volume C = e1.(e2 x e3)/6 - V0.
 __global__ void k_constraints(int64_t m, const int32_t *__restrict__ rv,
                               const double *__restrict__ rest_c, const double *__restrict__ x,
                               const double *__restrict__ y, const double *__restrict__ z,
@@ -41,45 +41,31 @@ __global__ void k_constraints(int64_t m, const int32_t *__restrict__ rv,
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m) return;
   const int32_t *v = rv + 4 * r;
-  double g[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) g[k] = 0.0;
+  double g[4][3];
   double val;
   if (v[2] < 0) {   // edge rows pad slots 2 and 3 with -1
-    int32_t i = v[0], j = v[1];
-    double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
-    double len = sqrt((dx * dx + dy * dy) + dz * dz);
-    if (len > 0.0) {
-      double nx = dx / len, ny = dy / len, nz = dz / len;
-      g[0] = nx; g[1] = ny; g[2] = nz;
-      g[3] = -nx; g[4] = -ny; g[5] = -nz;
-    }
-    val = len;
-  } else {
-    int32_t a = v[0], b = v[1], c = v[2], d = v[3];
-    double xa = x[a], ya = y[a], za = z[a];
-    double e1[3] = {x[b] - xa, y[b] - ya, z[b] - za};
-    double e2[3] = {x[c] - xa, y[c] - ya, z[c] - za};
-    double e3[3] = {x[d] - xa, y[d] - ya, z[d] - za};
-    double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2],
-                     e2[0] * e3[1] - e2[1] * e3[0]};
-    double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2],
-                     e3[0] * e1[1] - e3[1] * e1[0]};
-    double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                     e1[0] * e2[1] - e1[1] * e2[0]};
-    val = ((e1[0] * c23[0] + e1[1] * c23[1]) + e1[2] * c23[2]) / 6.0;
+    const int32_t i = v[0], j = v[1];
+    const double pi[3] = {x[i], y[i], z[i]}, pj[3] = {x[j], y[j], z[j]};
+    val = edge_grads(pi, pj, g[0], g[1]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      g[3 + k] = c23[k] / 6.0;
-      g[6 + k] = c31[k] / 6.0;
-      g[9 + k] = c12[k] / 6.0;
-      g[k] = -((g[3 + k] + g[6 + k]) + g[9 + k]);
+    for (int d = 0; d < 3; ++d) g[2][d] = g[3][d] = 0.0;
+  } else {
+    double p[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int32_t q = v[k];
+      p[k][0] = x[q];
+      p[k][1] = y[q];
+      p[k][2] = z[q];
     }
+    val = tet_grads(p[0], p[1], p[2], p[3], g) / 6.0;
   }
   C[r] = val - rest_c[r];
   double *go = grad + 12 * r;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) go[k] = g[k];
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) go[3 * k + d] = g[k][d];
 }
 void launch_constraints(int64_t m, const int32_t *rv, const double *rest_c,
                         const double *const *xyz, double *C, double *grad, hipStream_t s) {

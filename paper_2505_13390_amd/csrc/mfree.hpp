@@ -3,10 +3,14 @@
 // from the constraint gradients instead of the assembled CSR values (the
 // direction the Conclusion and Limitations section names for future work).
 // Two kernels per product: a vertex gather u_v = w_v sum_{c contains v}
-// g_{c,v} x_c over the vertex -> row incidence (ascending rows), then a row
-// pass (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c. The assembled A is
-// still built every global iteration: the setup, the Galerkin products and
-// the Jacobi diagonal read it.
+// g_{c,v} x_c over the vertex -> row incidence (ascending rows), reading the
+// gradient of each incidence from a vertex-major copy; then a row pass
+// (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c that recomputes the row's
+// gradients from the positions with the constraint kernel's own formulas
+// (grad.hpp), so it reads only the row's vertex ids from HBM. Both use
+// exactly the gradients the assembly used. The assembled A is still built
+// every global iteration: the setup, the Galerkin products and the Jacobi
+// diagonal read it.
 #pragma once
 
 #include "kernels.hpp"
@@ -17,23 +21,23 @@ template <class T>
 struct MfView {
   int64_t m = 0, nv = 0;
   const int32_t *rv = nullptr;    // [m][4] vertex ids of each row, -1 padded (edge rows)
-  const T *gp = nullptr;          // gradient planes: gp[(3k + d) m + c], slot k, component d
+  const T *pos = nullptr;         // [nv][4] positions (x, y, z, unused) of this iteration
   const T *alpha = nullptr;       // [m] alpha~ = alpha / dt^2
   const int64_t *vptr = nullptr;  // [nv + 1] incidence range of each vertex
   const int32_t *vrow = nullptr;  // [E] row of each incidence, ascending per vertex
   const T *gT = nullptr;          // [E][3] gradient of each incidence
   const T *w = nullptr;           // [nv] inverse masses
   T *u = nullptr;                 // [nv][4] scratch of the vertex gather
-  bool ok() const { return m > 0 && rv && gp && alpha && vptr && vrow && gT && w && u; }
+  bool ok() const { return m > 0 && rv && pos && alpha && vptr && vrow && gT && w && u; }
 };
 
-// Per global iteration, after the constraint kernel: gradient planes (edge
-// rows fill slot 0, volume rows slots 1-3; the remaining slot follows from
-// the others exactly as the constraint kernel formed it) and the per-incidence
-// gradients, converted to T.
+// Per global iteration, after the constraint kernel: positions as T
+// (pos[v] = (x, y, z)) and the per-incidence gradients gT[e] = the gradient
+// of slot vslot[e] of row vrow[e], converted to T.
 template <class T>
-void launch_mf_prepare(int64_t m, int64_t n_inc, const int32_t *rv, const double *grad,
-                       const int32_t *vrow, const int8_t *vslot, T *gp, T *gT, hipStream_t s);
+void launch_mf_prepare(int64_t nv, const double *x, const double *y, const double *z,
+                       int64_t n_inc, const int32_t *vrow, const int8_t *vslot,
+                       const double *grad, T *pos, T *gT, hipStream_t s);
 
 template <class T>
 void launch_mf_spmv(const MfView<T> &A, const T *x, T *y, const int *done, hipStream_t s);
