@@ -26,12 +26,11 @@ int lanes_for_rowlen(double mean) {
   }
 
 // Row-group kernel: G lanes per row, strided loads, fixed-tree lane sum.
-template <int G, class T, class Op>
+template <int G, class T, class In, class Op>
 __global__ __launch_bounds__(kBlock) void k_rows(const int *done, int64_t n,
                                                  const int64_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col,
-                                                 const T *__restrict__ val,
-                                                 const T *__restrict__ x, Op op,
+                                                 const T *__restrict__ val, In x, Op op,
                                                  double *partials) {
   if (done && *done) return;
   constexpr int R = kBlock / G;
@@ -45,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int *done, int64_t n,
     int64_t a = ok ? rp[i] : 0, b = ok ? rp[i + 1] : 0;
     T s = 0;
 #pragma unroll 4
-    for (int64_t e = a + sub; e < b; e += G) s += val[e] * x[col[e]];
+    for (int64_t e = a + sub; e < b; e += G) s += val[e] * x(col[e]);
     s = group_sum<G, T>(s);
     if (ok && sub == 0) op(i, s, acc);
   }
@@ -65,13 +64,12 @@ __device__ __forceinline__ V stream_load(const V *p) {
   else return *p;
 }
 
-template <int TILE, bool NT, class T, class Op>
+template <int TILE, bool NT, class T, class In, class Op>
 __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntiles,
                                                    const int64_t *__restrict__ tiles,
                                                    const int64_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col,
-                                                   const T *__restrict__ val,
-                                                   const T *__restrict__ x, Op op,
+                                                   const T *__restrict__ val, In x, Op op,
                                                    double *partials) {
   if (done && *done) return;
   constexpr int PER = TILE / kBlock;
@@ -95,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntil
       v[j] = in ? stream_load<NT>(val + e) : (T)0;
     }
 #pragma unroll
-    for (int j = 0; j < PER; ++j) prod[threadIdx.x + j * kBlock] = v[j] * x[c[j]];
+    for (int j = 0; j < PER; ++j) prod[threadIdx.x + j * kBlock] = v[j] * x(c[j]);
     __syncthreads();
     const int sub = threadIdx.x % LR;
     for (int64_t base = r0; base < r1; base += kBlock / LR) {
@@ -124,25 +122,25 @@ __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntil
     default: LAUNCH(2048); break;      \
   }
 
-template <class T, class Op>
-static int launch_pass(const CsrView<T> &A, const T *x, Op op, const int *done, double *partials,
+template <class T, class In, class Op>
+static int launch_pass(const CsrView<T> &A, In x, Op op, const int *done, double *partials,
                        hipStream_t s) {
   if (A.n == 0) return 0;
   if (A.tile > 0) {
     int grid = grid_for(A.ntiles, 1);
     if (A.nt) {
-#define L_(TL) k_stream<TL, true, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
+#define L_(TL) k_stream<TL, true, T, In, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
       MG_DISPATCH_TILE(A.tile, L_);
 #undef L_
     } else {
-#define L_(TL) k_stream<TL, false, T, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
+#define L_(TL) k_stream<TL, false, T, In, Op><<<grid, kBlock, 0, s>>>(done, A.ntiles, A.tiles, A.rowptr, A.col, A.val, x, op, partials)
       MG_DISPATCH_TILE(A.tile, L_);
 #undef L_
     }
     return grid;
   }
   int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_rows<G, T, Op><<<grid, kBlock, 0, s>>>(done, A.n, A.rowptr, A.col, A.val, x, op, partials)
+#define L_(G) k_rows<G, T, In, Op><<<grid, kBlock, 0, s>>>(done, A.n, A.rowptr, A.col, A.val, x, op, partials)
   MG_DISPATCH_G(A.lanes, L_);
 #undef L_
   return grid;
@@ -167,12 +165,12 @@ bool build_row_tiles(const std::vector<int64_t> &rp, int tile, std::vector<int64
 // ------------------------------------------------------------------ SpMV
 template <class T>
 void launch_spmv(const CsrView<T> &A, const T *x, T *y, hipStream_t s) {
-  launch_pass<T>(A, x, OpSpmv<T>{y}, nullptr, nullptr, s);
+  launch_pass<T>(A, InVec<T>{x}, OpSpmv<T>{y}, nullptr, nullptr, s);
 }
 
 int launch_spmv_dot_partials(const CsrView<double> &A, const double *p, double *q,
                              const int *done, double *partials, hipStream_t s) {
-  return launch_pass<double>(A, p, OpPcgDot{p, q}, done, partials, s);
+  return launch_pass<double>(A, InVec<double>{p}, OpPcgDot{p, q}, done, partials, s);
 }
 
 // ------------------------------------------------------------ smoother
@@ -195,12 +193,19 @@ void launch_jacobi_first(int64_t n, const T *wdinv, const T *r, T *z, const int 
 template <class T>
 void launch_jacobi(const CsrView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                    const int *done, hipStream_t s) {
-  launch_pass<T>(A, zi, OpJacobi<T>{wdinv, r, zi, zo}, done, nullptr, s);
+  launch_pass<T>(A, InVec<T>{zi}, OpJacobi<T, InVec<T>>{wdinv, r, InVec<T>{zi}, zo}, done,
+                 nullptr, s);
+}
+template <class T>
+void launch_jacobi_scaled(const CsrView<T> &A, const T *wdinv, const T *r, T *zo,
+                          const int *done, hipStream_t s) {
+  const InScaled<T> in{r, wdinv};
+  launch_pass<T>(A, in, OpJacobi<T, InScaled<T>>{wdinv, r, in, zo}, done, nullptr, s);
 }
 template <class T>
 void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
                      hipStream_t s) {
-  launch_pass<T>(A, z, OpResidual<T>{r, res}, done, nullptr, s);
+  launch_pass<T>(A, InVec<T>{z}, OpResidual<T>{r, res}, done, nullptr, s);
 }
 
 // ------------------------------------------------------------ transfers
@@ -675,6 +680,8 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
                                  const int *, hipStream_t);                                         \
   template void launch_residual<T>(const CsrView<T> &, const T *, const T *, T *, const int *,      \
                                    hipStream_t);                                                    \
+  template void launch_jacobi_scaled<T>(const CsrView<T> &, const T *, const T *, T *, const int *, \
+                                        hipStream_t);                                               \
   template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
                                    T *, const int *, hipStream_t);                                  \
   template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \

@@ -48,9 +48,8 @@ void launch_mf_prepare(int64_t nv, const double *x, const double *y, const doubl
 // ----------------------------------------------------------------- passes
 // u_v = w_v sum_{e in incidence(v)} gT_e x_{row(e)}; G lanes per vertex with a
 // fixed lane assignment and a fixed-tree sum.
-template <int G, class T>
-__global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T> A,
-                                                      const T *__restrict__ x) {
+template <int G, class T, class In>
+__global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T> A, In x) {
   if (done && *done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
@@ -63,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T>
     if (ok) {
       const int64_t a = A.vptr[v], b = A.vptr[v + 1];
       for (int64_t e = a + sub; e < b; e += G) {
-        const T xc = x[A.vrow[e]];
+        const T xc = x(A.vrow[e]);
         const T *g = A.gT + 3 * e;
         sx += g[0] * xc;
         sy += g[1] * xc;
@@ -88,52 +87,55 @@ __device__ __forceinline__ T dot_u(const T (&g)[3], const T *__restrict__ u) {
   return (g[0] * u[0] + g[1] * u[1]) + g[2] * u[2];
 }
 
-// (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c, one thread per row. The
-// slot gradients are formed one at a time (the same expressions as
-// tet_grads) and consumed at once, which keeps the register count low enough
-// for full occupancy.
-template <class T, class Op>
-__global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T> A,
-                                                    const T *__restrict__ x, Op op,
-                                                    double *partials) {
-  if (done && *done) return;
-  const int64_t m = A.m;
+// (J u)_c = sum_k g_{c,k} . u_{v_k} for row c. The slot gradients are formed
+// one at a time (the same expressions as tet_grads) and consumed at once,
+// which keeps the register count low enough for full occupancy.
+template <class T>
+__device__ __forceinline__ T mf_row(const MfView<T> &A, int64_t c) {
   const T *__restrict__ pos = A.pos;
   const T *__restrict__ u = A.u;
+  const int4 r = *reinterpret_cast<const int4 *>(A.rv + 4 * c);
+  const int64_t va = r.x, vb = r.y;
+  T s;
+  if (r.z < 0) {
+    T g0[3], g1[3];
+    edge_grads(pos + 4 * va, pos + 4 * vb, g0, g1);
+    s = dot_u(g0, u + 4 * va);
+    s += dot_u(g1, u + 4 * vb);
+  } else {
+    const int64_t vc = r.z, vd = r.w;
+    T e1[3], e2[3], e3[3], cr[3], g1[3], g2[3], g3[3], g0[3];
+    tet_edges(pos + 4 * va, pos + 4 * vb, pos + 4 * vc, pos + 4 * vd, e1, e2, e3);
+    cross(e2, e3, cr);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g1[d] = cr[d] / (T)6;
+    cross(e3, e1, cr);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g2[d] = cr[d] / (T)6;
+    cross(e1, e2, cr);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      g3[d] = cr[d] / (T)6;
+      g0[d] = -((g1[d] + g2[d]) + g3[d]);
+    }
+    s = dot_u(g0, u + 4 * va);
+    s += dot_u(g1, u + 4 * vb);
+    s += dot_u(g2, u + 4 * vc);
+    s += dot_u(g3, u + 4 * vd);
+  }
+  return s;
+}
+
+// (A x)_c = (J u)_c + alpha~_c x_c, one thread per row, then the epilogue.
+template <class T, class In, class Op>
+__global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T> A, In x, Op op,
+                                                       double *partials) {
+  if (done && *done) return;
   int64_t lo, hi;
-  block_range(m, lo, hi);
+  block_range(A.m, lo, hi);
   double acc = 0.0;
   for (int64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
-    const int4 r = *reinterpret_cast<const int4 *>(A.rv + 4 * c);
-    const int64_t va = r.x, vb = r.y;
-    T s;
-    if (r.z < 0) {
-      T g0[3], g1[3];
-      edge_grads(pos + 4 * va, pos + 4 * vb, g0, g1);
-      s = dot_u(g0, u + 4 * va);
-      s += dot_u(g1, u + 4 * vb);
-    } else {
-      const int64_t vc = r.z, vd = r.w;
-      T e1[3], e2[3], e3[3], cr[3], g1[3], g2[3], g3[3], g0[3];
-      tet_edges(pos + 4 * va, pos + 4 * vb, pos + 4 * vc, pos + 4 * vd, e1, e2, e3);
-      cross(e2, e3, cr);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) g1[d] = cr[d] / (T)6;
-      cross(e3, e1, cr);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) g2[d] = cr[d] / (T)6;
-      cross(e1, e2, cr);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        g3[d] = cr[d] / (T)6;
-        g0[d] = -((g1[d] + g2[d]) + g3[d]);
-      }
-      s = dot_u(g0, u + 4 * va);
-      s += dot_u(g1, u + 4 * vb);
-      s += dot_u(g2, u + 4 * vc);
-      s += dot_u(g3, u + 4 * vd);
-    }
-    s = s + A.alpha[c] * x[c];
+    const T s = mf_row(A, c) + A.alpha[c] * x(c);
     op(c, s, acc);
   }
   if (partials) {
@@ -142,49 +144,54 @@ __global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T
   }
 }
 
-template <class T, class Op>
-static int launch_mf_pass(const MfView<T> &A, const T *x, Op op, const int *done,
-                          double *partials, hipStream_t s) {
+template <class T, class In>
+static void launch_mf_gather_in(const MfView<T> &A, In x, const int *done, hipStream_t s) {
+  if (A.m && A.nv)
+    k_mf_gather<kMfLanes, T, In><<<grid_for(A.nv * kMfLanes, kBlock), kBlock, 0, s>>>(done, A, x);
+}
+
+template <class T, class In, class Op>
+static int launch_mf_pass(const MfView<T> &A, In x, Op op, const int *done, double *partials,
+                          hipStream_t s) {
   if (!A.m) return 0;
-  if (A.nv)
-    k_mf_gather<kMfLanes, T><<<grid_for(A.nv * kMfLanes, kBlock), kBlock, 0, s>>>(done, A, x);
+  launch_mf_gather_in<T>(A, x, done, s);
   const int grid = grid_for(A.m, kBlock);
-  k_mf_rows<T, Op><<<grid, kBlock, 0, s>>>(done, A, x, op, partials);
+  k_mf_rows<T, In, Op><<<grid, kBlock, 0, s>>>(done, A, x, op, partials);
   return grid;
 }
 
 template <class T>
 void launch_mf_spmv(const MfView<T> &A, const T *x, T *y, const int *done, hipStream_t s) {
-  launch_mf_pass<T>(A, x, OpSpmv<T>{y}, done, nullptr, s);
+  launch_mf_pass<T>(A, InVec<T>{x}, OpSpmv<T>{y}, done, nullptr, s);
 }
 template <class T>
 void launch_mf_jacobi(const MfView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                       const int *done, hipStream_t s) {
-  launch_mf_pass<T>(A, zi, OpJacobi<T>{wdinv, r, zi, zo}, done, nullptr, s);
+  const InVec<T> in{zi};
+  launch_mf_pass<T>(A, in, OpJacobi<T, InVec<T>>{wdinv, r, in, zo}, done, nullptr, s);
 }
 template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s) {
-  launch_mf_pass<T>(A, z, OpResidual<T>{r, res}, done, nullptr, s);
+  launch_mf_pass<T>(A, InVec<T>{z}, OpResidual<T>{r, res}, done, nullptr, s);
 }
-
 void launch_mf_gather(const MfView<double> &A, const double *x, const int *done, hipStream_t s) {
-  if (A.m && A.nv)
-    k_mf_gather<kMfLanes, double>
-        <<<grid_for(A.nv * kMfLanes, kBlock), kBlock, 0, s>>>(done, A, x);
+  launch_mf_gather_in<double>(A, InVec<double>{x}, done, s);
 }
 int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, const int *done,
                        double *partials, hipStream_t s) {
   if (!A.m) return 0;
   const int grid = grid_for(A.m, kBlock);
-  k_mf_rows<double, OpPcgDot><<<grid, kBlock, 0, s>>>(done, A, p, OpPcgDot{p, q}, partials);
+  k_mf_rows<double, InVec<double>, OpPcgDot>
+      <<<grid, kBlock, 0, s>>>(done, A, InVec<double>{p}, OpPcgDot{p, q}, partials);
   return grid;
 }
 
 void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *p, double *q,
                             double *partials, hipStream_t s) {
   const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field
-  const int grid = launch_mf_pass<double>(A, p, OpPcgDot{p, q}, done, partials, s);
+  const int grid =
+      launch_mf_pass<double>(A, InVec<double>{p}, OpPcgDot{p, q}, done, partials, s);
   launch_fin_pq(ctl, partials, grid, s);
 }
 

@@ -46,6 +46,10 @@ template <class T> void launch_jacobi(const CsrView<T> &A, const T *wdinv, const
 // res = r - A z
 template <class T> void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res,
                                         const int *done, hipStream_t s);
+// the first two sweeps from z = 0 in one pass: zo = z1 + omega D^-1 (r - A z1)
+// with z1 = omega D^-1 r formed on the fly
+template <class T> void launch_jacobi_scaled(const CsrView<T> &A, const T *wdinv, const T *r,
+                                             T *zo, const int *done, hipStream_t s);
 // rc[a] = sum over members i of a (ascending) of p_i res_i
 template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
                                         const int32_t *agg_mem, const T *p, const T *res, T *rc,

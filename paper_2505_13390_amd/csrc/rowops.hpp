@@ -13,12 +13,26 @@ struct OpSpmv {
   T *y;
   __device__ void operator()(int64_t i, T s, double &) const { y[i] = s; }
 };
+// Input vectors of a pass, read through a functor so that an elementwise
+// step before the product (the first Jacobi sweep from zero) is applied on
+// the fly instead of in a kernel of its own.
 template <class T>
+struct InVec {  // x_j
+  const T *x;
+  __device__ __forceinline__ T operator()(int64_t j) const { return x[j]; }
+};
+template <class T>
+struct InScaled {  // the first sweep from z = 0: z_j = omega D^-1 r, as r_j * wdinv_j
+  const T *r, *wdinv;
+  __device__ __forceinline__ T operator()(int64_t j) const { return r[j] * wdinv[j]; }
+};
+template <class T, class In>
 struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi), wdinv = omega D^-1 per row
-  const T *wdinv, *r, *zi;
+  const T *wdinv, *r;
+  In zi;
   T *zo;
   __device__ void operator()(int64_t i, T s, double &) const {
-    zo[i] = zi[i] + (r[i] - s) * wdinv[i];
+    zo[i] = zi(i) + (r[i] - s) * wdinv[i];
   }
 };
 template <class T>

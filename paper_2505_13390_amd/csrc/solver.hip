@@ -135,8 +135,10 @@ void Solver::finish_level(int l) {
   MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN,
              "level " + std::to_string(l) + " has a non-positive diagonal entry");
   // vectors of the V-cycle
-  L.r.alloc(L.n); L.z.alloc(L.n); L.t.alloc(L.n); L.res.alloc(L.n);
-  if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); L.res32.alloc(L.n); }
+  L.r.alloc(L.n); L.z.alloc(L.n); L.t.alloc(L.n);
+  if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); }
+  L.res.alloc(L.n);
+  if (mixed()) L.res32.alloc(L.n);
   power_omega(l);
   L.d_omega.upload(L.omega.data(), L.omega.size(), st);
   launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p, mixed() ? L.wdinv32.p : nullptr,
@@ -382,6 +384,9 @@ void Solver::build_members(int l) {
   L.agg_mem.alloc(std::max<int64_t>(nmem, 1));
   launch_scatter_members(L.n, L.agg.p, L.agg_ptr.p, itmp.p, L.agg_mem.p, st);
   launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
+  // lanes per aggregate of the fused matrix-free residual + restriction
+  const double mean = na ? (double)nmem / (double)na : 1.0;
+  L.rlanes = mean <= 16.0 ? 8 : mean <= 32.0 ? 16 : mean <= 64.0 ? 32 : 64;
 }
 
 void Solver::galerkin_symbolic(int l) {
@@ -618,30 +623,6 @@ const MfView<float> *Solver::level_mf<float>(int l) const {
   return (l == 0 && mf32.ok()) ? &mf32 : nullptr;
 }
 
-// `sweeps` weighted Jacobi sweeps; from_zero: the iterate starts at 0 and the
-// first sweep is z = omega D^-1 r
-template <class T>
-void Solver::smooth(int l, const T *r, T *&a, T *&b, int sweeps, bool from_zero) {
-  Level &L = *lev[l];
-  const int *done = done_ptr();
-  CsrView<T> A = Buf<T>::A(L);
-  const MfView<T> *M = level_mf<T>(l);
-  const T *wd = Buf<T>::wdinv(L);
-  int k = 0;
-  if (from_zero) {
-    // the first sweep from z = 0 is elementwise; fusing it into the second
-    // would gather both r and D^-1 per entry, which costs more than the extra
-    // pass over three vectors
-    if (sweeps >= 1) { launch_jacobi_first<T>(L.n, wd, r, a, done, st); k = 1; }
-    else { launch_zero_t<T>(L.n, a, done, st); }
-  }
-  for (; k < sweeps; ++k) {
-    if (M) launch_mf_jacobi<T>(*M, wd, r, a, b, done, st);
-    else launch_jacobi<T>(A, wd, r, a, b, done, st);
-    std::swap(a, b);
-  }
-}
-
 template <class T>
 void Solver::vcycle(int l, const T *r, T *z) {
   Level &L = *lev[l];
@@ -651,22 +632,59 @@ void Solver::vcycle(int l, const T *r, T *z) {
                                 Ainv.p, r, z, done, st);
     return;
   }
-  // start in the buffer that makes the last sweep land in z
-  const int swaps = (opt.pre_sweeps > 0 ? opt.pre_sweeps - 1 : 0) + opt.post_sweeps;
-  T *a = z, *b = Buf<T>::t(L).p;
-  if (swaps % 2) std::swap(a, b);
-  smooth<T>(l, r, a, b, opt.pre_sweeps, true);
-  if (l + 1 < nlev) {
-    Level &C = *lev[l + 1];
-    T *res = Buf<T>::res(L).p;
-    if (const MfView<T> *M = level_mf<T>(l)) launch_mf_residual<T>(*M, r, a, res, done, st);
-    else launch_residual<T>(Buf<T>::A(L), r, a, res, done, st);
-    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, Buf<T>::r(C).p, done, st);
-    vcycle<T>(l + 1, Buf<T>::r(C).p, Buf<T>::z(C).p);
-    launch_prolong<T>(L.n, L.agg.p, Buf<T>::p(L), Buf<T>::z(C).p, a, done, st);
+  const int pre = opt.pre_sweeps, post = opt.post_sweeps;
+  const bool coarse = l + 1 < nlev;
+  const MfView<T> *M = level_mf<T>(l);
+  const CsrView<T> A = Buf<T>::A(L);
+  const T *wd = Buf<T>::wdinv(L);
+  // On CSR levels the first two sweeps from zero are one pass that forms
+  // z1 = omega D^-1 r on the fly. A matrix-free level keeps the elementwise
+  // first sweep: its gather would fetch two vectors per incidence instead of
+  // one, which costs more than the separate kernel.
+  const bool fuse = (M == nullptr);
+  // The iterate ping-pongs between z and the level's scratch vector; the
+  // first target is chosen so that the last write lands in z.
+  const int pre_writes = pre == 0 ? 1 : (fuse && pre >= 2) ? pre - 1 : pre;
+  const int writes = pre_writes + post;
+  T *bufs[2] = {z, Buf<T>::t(L).p};
+  int w = (writes % 2) ? 0 : 1;
+  auto next = [&]() { return bufs[(w++) % 2]; };
+  auto sweep = [&](const T *zi, T *zo) {
+    if (M) launch_mf_jacobi<T>(*M, wd, r, zi, zo, done, st);
+    else launch_jacobi<T>(A, wd, r, zi, zo, done, st);
+  };
+  T *cur = next();
+  int k0 = 1;
+  if (pre == 0) {
+    launch_zero_t<T>(L.n, cur, done, st);
+  } else if (fuse && pre >= 2) {
+    launch_jacobi_scaled<T>(A, wd, r, cur, done, st);
+    k0 = 2;
+  } else {
+    launch_jacobi_first<T>(L.n, wd, r, cur, done, st);
   }
-  smooth<T>(l, r, a, b, opt.post_sweeps, false);
-  if (a != z) launch_copy_t<T>(L.n, a, z, done, st);
+  for (int k = k0; k < pre; ++k) {
+    T *o = next();
+    sweep(cur, o);
+    cur = o;
+  }
+  if (coarse) {
+    Level &C = *lev[l + 1];
+    T *rc = Buf<T>::r(C).p, *ec = Buf<T>::z(C).p;
+    const T *pl = Buf<T>::p(L);
+    T *res = Buf<T>::res(L).p;
+    if (M) launch_mf_residual<T>(*M, r, cur, res, done, st);
+    else launch_residual<T>(A, r, cur, res, done, st);
+    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, pl, res, rc, done, st);
+    vcycle<T>(l + 1, rc, ec);
+    launch_prolong<T>(L.n, L.agg.p, pl, ec, cur, done, st);
+  }
+  for (int k = 0; k < post; ++k) {
+    T *o = next();
+    sweep(cur, o);
+    cur = o;
+  }
+  if (cur != z) launch_copy_t<T>(L.n, cur, z, done, st);   // not reached: w makes cur == z
   // bodies that end here with a dense solve: their rows are that solve's
   if (!L.jobs.empty())
     launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,

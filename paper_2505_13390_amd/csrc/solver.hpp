@@ -48,6 +48,7 @@ struct Level {
   // transfer to the next level
   bool has_next = false;
   int64_t n_agg = 0;
+  int rlanes = 8;   // lanes per aggregate in the fused matrix-free residual + restriction
   DevBuf<int32_t> agg;
   DevBuf<int64_t> agg_ptr;
   DevBuf<int32_t> agg_mem;
@@ -172,7 +173,6 @@ class Solver {
   void factor_dense();
   void iterate_once(int k);
   template <class T> void vcycle(int l, const T *r, T *z);
-  template <class T> void smooth(int l, const T *r, T *&a, T *&b, int sweeps, bool from_zero);
   template <class T> const MfView<T> *level_mf(int l) const;
 };
 
