@@ -6,9 +6,12 @@
 #include "mfree.hpp"
 #include "rowops.hpp"
 
+
 namespace mgpbd {
 
-constexpr int kMfLanes = 8;   // lanes per vertex in the gather (about 36 rows per vertex)
+// lanes per vertex in the gather (about 36 rows per vertex; 16 measured fastest of
+// 4 to 64 on the 32x32x128 beam)
+constexpr int kMfLanes = 16;
 
 // ---------------------------------------------------------------- prepare
 template <class T>
@@ -91,10 +94,9 @@ __device__ __forceinline__ T dot_u(const T (&g)[3], const T *__restrict__ u) {
 // one at a time (the same expressions as tet_grads) and consumed at once,
 // which keeps the register count low enough for full occupancy.
 template <class T>
-__device__ __forceinline__ T mf_row(const MfView<T> &A, int64_t c) {
+__device__ __forceinline__ T mf_row(const MfView<T> &A, const int4 r) {
   const T *__restrict__ pos = A.pos;
   const T *__restrict__ u = A.u;
-  const int4 r = *reinterpret_cast<const int4 *>(A.rv + 4 * c);
   const int64_t va = r.x, vb = r.y;
   T s;
   if (r.z < 0) {
@@ -134,8 +136,15 @@ __global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T
   int64_t lo, hi;
   block_range(A.m, lo, hi);
   double acc = 0.0;
-  for (int64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
-    const T s = mf_row(A, c) + A.alpha[c] * x(c);
+  const int4 *rv4 = reinterpret_cast<const int4 *>(A.rv);
+  // the vertex ids of the next row are loaded while this row is computed
+  int64_t c = lo + threadIdx.x;
+  int4 rn = c < hi ? rv4[c] : make_int4(0, 0, -1, -1);
+  for (; c < hi; c += blockDim.x) {
+    const int4 r = rn;
+    const int64_t cn = c + blockDim.x;
+    if (cn < hi) rn = rv4[cn];
+    const T s = mf_row(A, r) + A.alpha[c] * x(c);
     op(c, s, acc);
   }
   if (partials) {

@@ -336,31 +336,64 @@ void launch_color_keys(int64_t n, uint64_t salt, uint64_t *key, hipStream_t s) {
   if (n) k_color_keys<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, salt, key);
 }
 
+// Jones-Plassmann colouring driven by counters: cnt[i] = number of
+// neighbours with a higher key; a row is coloured once that count reaches
+// zero (all higher-priority neighbours coloured), with the smallest colour
+// none of them uses, which is exactly the greedy colouring in descending key
+// order. Each round colours one frontier and decrements the counters of the
+// lower-priority neighbours; rows reaching zero form the next frontier.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_color_round(int64_t n, const int64_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_color_count(int64_t n, const int64_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
                                                         const uint64_t *__restrict__ key,
-                                                        int32_t *color, int *remaining,
-                                                        int *overflow) {
+                                                        int32_t *__restrict__ cnt,
+                                                        int32_t *__restrict__ front, int *nfront) {
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
   int64_t lo, hi;
   block_range(n, lo, hi);
   for (int64_t base = lo; base < hi; base += R) {
-    int64_t i = base + grp;
-    bool ok = i < hi;
-    bool todo = ok && color[i] < 0;
-    uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-    int wait = 0, over = 0;
-    if (todo) {
-      uint64_t ki = key[i];
+    const int64_t i = base + grp;
+    const bool ok = i < hi;
+    int c = 0;
+    if (ok) {
+      const uint64_t ki = key[i];
       for (int64_t e = rp[i] + sub; e < rp[i + 1]; e += G) {
-        int32_t j = col[e];
-        if (j == (int32_t)i || key[j] < ki) continue;
-        int32_t cj = color[j];   // a stale -1 only postpones this row to a later round
-        if (cj < 0) { wait = 1; continue; }
-        if (cj >= kMaxColors) { over = 1; continue; }
-        uint64_t bit = 1ULL << (cj & 63);
+        const int32_t j = col[e];
+        if (j != (int32_t)i && key[j] > ki) ++c;
+      }
+    }
+    c = group_sum<G, int>(c);
+    if (ok && sub == 0) {
+      cnt[i] = c;
+      if (c == 0) front[atomicAdd(nfront, 1)] = (int32_t)i;
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_color_front(
+    int64_t nf, const int32_t *__restrict__ front, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const uint64_t *__restrict__ key, int32_t *color,
+    int32_t *cnt, int32_t *__restrict__ next, int *nnext, int *overflow) {
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(nf, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    const int64_t f = base + grp;
+    const bool ok = f < hi;
+    const int32_t i = ok ? front[f] : 0;
+    uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    int over = 0;
+    if (ok) {
+      const uint64_t ki = key[i];
+      for (int64_t e = rp[i] + sub; e < rp[i + 1]; e += G) {
+        const int32_t j = col[e];
+        if (j == i || key[j] < ki) continue;
+        const int32_t cj = color[j];
+        if (cj < 0 || cj >= kMaxColors) { over = 1; continue; }
+        const uint64_t bit = 1ULL << (cj & 63);
         if (cj < 64) m0 |= bit; else if (cj < 128) m1 |= bit; else if (cj < 192) m2 |= bit; else m3 |= bit;
       }
     }
@@ -370,26 +403,42 @@ __global__ __launch_bounds__(kBlock) void k_color_round(int64_t n, const int64_t
       m1 |= __shfl_xor(m1, off, G);
       m2 |= __shfl_xor(m2, off, G);
       m3 |= __shfl_xor(m3, off, G);
-      wait |= __shfl_xor(wait, off, G);
       over |= __shfl_xor(over, off, G);
     }
-    if (todo && sub == 0) {
-      if (over) { atomicExch(overflow, 1); continue; }
-      if (wait) { atomicAdd(remaining, 1); continue; }
-      int c;
+    if (!ok) continue;
+    if (sub == 0) {
+      int c = -1;
       if (~m0) c = __ffsll((long long)~m0) - 1;
       else if (~m1) c = 64 + __ffsll((long long)~m1) - 1;
       else if (~m2) c = 128 + __ffsll((long long)~m2) - 1;
       else if (~m3) c = 192 + __ffsll((long long)~m3) - 1;
-      else { atomicExch(overflow, 1); continue; }
-      color[i] = c;
+      if (over || c < 0) atomicExch(overflow, 1);
+      color[i] = c < 0 ? kMaxColors : c;
+    }
+    // release the lower-priority neighbours (the colour is read in a later launch)
+    const uint64_t ki = key[i];
+    for (int64_t e = rp[i] + sub; e < rp[i + 1]; e += G) {
+      const int32_t j = col[e];
+      if (j == i || key[j] > ki) continue;
+      if (atomicSub(&cnt[j], 1) == 1) next[atomicAdd(nnext, 1)] = j;
     }
   }
 }
-void launch_color_round(const CsrView<double> &A, const uint64_t *key, int32_t *color,
-                        int *remaining, int *overflow, hipStream_t s) {
-  int grid = grid_for(A.n * A.lanes, kBlock);
-#define L_(G) k_color_round<G><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, key, color, remaining, overflow)
+
+void launch_color_count(const CsrView<double> &A, const uint64_t *key, int32_t *cnt,
+                        int32_t *front, int *nfront, hipStream_t s) {
+  if (!A.n) return;
+  const int grid = grid_for(A.n * A.lanes, kBlock);
+#define L_(G) k_color_count<G><<<grid, kBlock, 0, s>>>(A.n, A.rowptr, A.col, key, cnt, front, nfront)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+void launch_color_front(const CsrView<double> &A, int64_t nf, const int32_t *front,
+                        const uint64_t *key, int32_t *color, int32_t *cnt, int32_t *next,
+                        int *nnext, int *overflow, hipStream_t s) {
+  if (!nf) return;
+  const int grid = grid_for(nf * A.lanes, kBlock);
+#define L_(G) k_color_front<G><<<grid, kBlock, 0, s>>>(nf, front, A.rowptr, A.col, key, color, cnt, next, nnext, overflow)
   MG_DISPATCH_G(A.lanes, L_);
 #undef L_
 }

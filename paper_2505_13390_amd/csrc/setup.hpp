@@ -32,8 +32,13 @@ void launch_sort_segments(int64_t nseg, const int64_t *ptr, int32_t *mem, hipStr
 
 // Jones-Plassmann greedy colouring over the structural graph
 void launch_color_keys(int64_t n, uint64_t salt, uint64_t *key, hipStream_t s);
-void launch_color_round(const CsrView<double> &A, const uint64_t *key, int32_t *color,
-                        int *remaining, int *overflow, hipStream_t s);
+// Jones-Plassmann by counters: higher-key neighbour counts and the first
+// frontier (rows with none), then one launch per frontier
+void launch_color_count(const CsrView<double> &A, const uint64_t *key, int32_t *cnt,
+                        int32_t *front, int *nfront, hipStream_t s);
+void launch_color_front(const CsrView<double> &A, int64_t nf, const int32_t *front,
+                        const uint64_t *key, int32_t *color, int32_t *cnt, int32_t *next,
+                        int *nnext, int *overflow, hipStream_t s);
 void launch_count_colors(int64_t n, const int32_t *color, int32_t *cnt, hipStream_t s);
 void launch_scatter_colors(int64_t n, const int32_t *color, const int64_t *off, int32_t *cursor,
                            int32_t *rows, hipStream_t s);

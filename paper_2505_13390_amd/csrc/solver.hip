@@ -337,15 +337,26 @@ void Solver::candidate0() {
   L.color.alloc(n);
   launch_s_color_keys(t, stream_salt(opt.seed, kStreamColorPrio), key.p, st);
   launch_fill_i32(n, -1, L.color.p, st);
-  for (int round = 0;; ++round) {
-    MG_REQUIRE(round < 1000000, MGPBD_E_SETUP, "colouring did not terminate");
+  {
+    itmp.reserve(n);             // higher-priority neighbour counts
+    DevBuf<int32_t> fr[2];
+    fr[0].alloc(std::max<int64_t>(n, 1));
+    fr[1].alloc(std::max<int64_t>(n, 1));
     reset_flags();
-    launch_color_round(A, key.p, L.color.p, flags.p + kFRemaining, flags.p + kFColorOver, st);
-    int *h = static_cast<int *>(pinned);
-    MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
-    MG_HIP(hipStreamSynchronize(st));
-    MG_REQUIRE(h[kFColorOver] == 0, MGPBD_E_SETUP, "more than 256 colours needed");
-    if (h[kFRemaining] == 0) break;
+    launch_color_count(A, key.p, itmp.p, fr[0].p, flags.p + kFRemaining, st);
+    int64_t nf = read_flag(kFRemaining), done_rows = 0;
+    for (int round = 0; nf > 0; ++round) {
+      MG_REQUIRE(round < 1000000, MGPBD_E_SETUP, "colouring did not terminate");
+      done_rows += nf;
+      MG_REQUIRE(done_rows <= n, MGPBD_E_SETUP, "colouring frontier overflow");
+      const int cur = round & 1;
+      MG_HIP(hipMemsetAsync(flags.p + kFRemaining, 0, sizeof(int), st));
+      launch_color_front(A, nf, fr[cur].p, key.p, L.color.p, itmp.p, fr[cur ^ 1].p,
+                         flags.p + kFRemaining, flags.p + kFColorOver, st);
+      nf = read_flag(kFRemaining);
+    }
+    MG_REQUIRE(read_flag(kFColorOver) == 0, MGPBD_E_SETUP, "more than 256 colours needed");
+    MG_REQUIRE(done_rows == n, MGPBD_E_SETUP, "colouring left rows uncoloured");
   }
   // rows grouped by colour
   itmp.reserve(256);
