@@ -9,24 +9,6 @@
 
 namespace mgpbd {
 
-__global__ void k_zero_dense(int64_t nn, double *D) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nn) D[i] = 0.0;
-}
-__global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rp,
-                               const int32_t *__restrict__ col, const double *__restrict__ val,
-                               double *__restrict__ D) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) D[i * n + col[e]] = val[e];
-}
-void launch_csr_to_dense(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
-                         double *D, hipStream_t s) {
-  if (!n) return;
-  k_zero_dense<<<blocks_for(n * n, kBlock), kBlock, 0, s>>>(n * n, D);
-  k_csr_to_dense<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, rp, col, val, D);
-}
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C(16x16 tile at r0, c0) -= A(r0.., k0..k0+kk) * B(c0.., k0..k0+kk)^T with
@@ -137,35 +119,6 @@ __device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
     }
   }
   return 0;
-}
-
-__global__ __launch_bounds__(256) void k_chol_inverse(int64_t n, int64_t np, double *__restrict__ D,
-                                                      double *__restrict__ Y,
-                                                      double *__restrict__ Ainv, int *status) {
-  int bad = chol_inverse_block(n, np, D, Y, Ainv);
-  if (threadIdx.x == 0) *status = bad;
-}
-
-__global__ void k_pad_dense(int64_t n, int64_t np, const double *__restrict__ D,
-                            double *__restrict__ P) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= np * np) return;
-  int64_t i = idx / np, k = idx % np;
-  double v;
-  if (i < n && k < n) v = D[i * n + k];
-  else v = (i == k) ? 1.0 : 0.0;
-  P[idx] = v;
-}
-
-// D: n x n input (destroyed); Y: scratch of np x np; the padded factor is
-// formed in Y's companion region, so Y must hold 2 np^2 doubles.
-void launch_chol_inverse(int64_t n, double *D, double *Y, double *Ainv, int *status,
-                         hipStream_t s) {
-  if (!n) return;
-  int64_t np = (n + 15) / 16 * 16;
-  double *Pd = Y + np * np;   // padded copy of D
-  k_pad_dense<<<blocks_for(np * np, kBlock), kBlock, 0, s>>>(n, np, D, Pd);
-  k_chol_inverse<<<1, 256, 0, s>>>(n, np, Pd, Y, Ainv, status);
 }
 
 // ------------------------------------------------------------ dense batch

@@ -263,29 +263,6 @@ void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec, T *z
   k_prolong<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, agg, p, ec, z, done);
 }
 
-// one wavefront per row of the dense inverse
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_dense_apply(int64_t n, const double *__restrict__ Ainv,
-                                                        const T *__restrict__ rc,
-                                                        T *__restrict__ ec, const int *done) {
-  if (done && *done) return;
-  const int lane = threadIdx.x % kWave;
-  int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  bool ok = row < n;
-  double s = 0.0;
-  if (ok)
-    for (int64_t k = lane; k < n; k += kWave) s += Ainv[row * n + k] * (double)rc[k];
-  s = group_sum<kWave>(s);
-  if (ok && lane == 0) ec[row] = (T)s;
-}
-
-template <class T>
-void launch_dense_apply(int64_t n, const double *Ainv, const T *rc, T *ec, const int *done,
-                        hipStream_t s) {
-  if (n == 0) return;
-  k_dense_apply<T><<<blocks_for(n, kBlock / kWave), kBlock, 0, s>>>(n, Ainv, rc, ec, done);
-}
-
 // ------------------------------------------------------------ utilities
 __global__ void k_d2f(int64_t n, const double *__restrict__ in, float *__restrict__ out,
                       const int *done) {
@@ -356,77 +333,8 @@ void launch_fill_u8(int64_t n, uint8_t v, uint8_t *out, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ PCG
-// Each reduction is a producing kernel (block partials) followed by a
-// one-block finisher that updates the control block.
-__global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n, const double *__restrict__ b,
-                                                     double *__restrict__ x,
-                                                     double *__restrict__ r, double *partials) {
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double bi = b[i];
-    x[i] = 0.0;
-    r[i] = bi;
-    v[0] += bi * bi;
-  }
-  block_partials<1>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_init(PcgCtl *ctl, const double *partials,
-                                                     int nparts) {
-  double tot[1];
-  sum_partials<1>(partials, nparts, tot);
-  if (threadIdx.x == 0) {
-    ctl->bnorm = sqrt(tot[0]);
-    ctl->iters = 0;
-    ctl->ratio = 0.0;
-    ctl->rr = tot[0];
-    ctl->done = (ctl->bnorm == 0.0) ? 1 : 0;
-    if (!(tot[0] == tot[0]) || tot[0] > 1.7976931348623157e308) ctl->done = 2;
-  }
-}
-void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double *r, RedBuf rb,
-                     hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_pcg_init<<<grid, kBlock, 0, s>>>(n, b, x, r, rb.partials);
-  k_fin_init<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
-}
-
-__global__ __launch_bounds__(kBlock) void k_pcg_init_p(const PcgCtl *ctl, int64_t n,
-                                                       const double *__restrict__ r,
-                                                       const double *__restrict__ z,
-                                                       double *__restrict__ p,
-                                                       double *__restrict__ zold, int flexible,
-                                                       double *partials) {
-  if (ctl->done) return;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double zi = z[i];
-    p[i] = zi;
-    if (flexible) zold[i] = zi;
-    v[0] += r[i] * zi;
-  }
-  block_partials<1>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_init_p(PcgCtl *ctl, const double *partials,
-                                                       int nparts) {
-  if (ctl->done) return;
-  double tot[1];
-  sum_partials<1>(partials, nparts, tot);
-  if (threadIdx.x == 0) {
-    ctl->rho = tot[0];
-    if (!(tot[0] > 0.0)) ctl->done = 2;
-  }
-}
-void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
-                       double *zold, bool flexible, RedBuf rb, hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_pcg_init_p<<<grid, kBlock, 0, s>>>(ctl, n, r, z, p, zold, flexible ? 1 : 0, rb.partials);
-  k_fin_init_p<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
-}
-
+// Finisher of the fused product + dot of one solve (the other PCG kernels,
+// for one body or several, are the segmented ones).
 __global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *partials,
                                                    int nparts) {
   if (ctl->done) return;
@@ -440,135 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_pq(PcgCtl *ctl, const double *pa
 }
 void launch_fin_pq(PcgCtl *ctl, const double *partials, int nparts, hipStream_t s) {
   k_fin_pq<<<1, kBlock, 0, s>>>(ctl, partials, nparts);
-}
-void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
-                         RedBuf rb, hipStream_t s) {
-  const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field
-  int grid = launch_spmv_dot_partials(A, p, q, done, rb.partials, s);
-  k_fin_pq<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
-}
-
-__global__ __launch_bounds__(kBlock) void k_pcg_update(const PcgCtl *ctl, int64_t n,
-                                                       const double *__restrict__ p,
-                                                       const double *__restrict__ q,
-                                                       double *__restrict__ x,
-                                                       double *__restrict__ r, double *partials) {
-  if (ctl->done) return;
-  const double alpha = ctl->alpha;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    x[i] = x[i] + alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    v[0] += ri * ri;
-  }
-  block_partials<1>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_update(PcgCtl *ctl, const double *partials,
-                                                       int nparts) {
-  if (ctl->done) return;
-  double tot[1];
-  sum_partials<1>(partials, nparts, tot);
-  if (threadIdx.x == 0) {
-    int it = ctl->iters + 1;
-    ctl->iters = it;
-    ctl->rr = tot[0];
-    double ratio = sqrt(tot[0]) / ctl->bnorm;
-    ctl->ratio = ratio;
-    if (!(ratio == ratio)) ctl->done = 2;
-    else if (ctl->force > 0) { if (it >= ctl->force) ctl->done = 3; }
-    else if (ratio <= ctl->tol) ctl->done = 1;
-    else if (it >= ctl->max_iters) ctl->done = 4;
-  }
-}
-void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,
-                       double *r, RedBuf rb, hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_pcg_update<<<grid, kBlock, 0, s>>>(ctl, n, p, q, x, r, rb.partials);
-  k_fin_update<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid);
-}
-
-__global__ __launch_bounds__(kBlock) void k_pcg_rz(const PcgCtl *ctl, int64_t n,
-                                                   const double *__restrict__ r,
-                                                   double *__restrict__ z,
-                                                   const float *__restrict__ z32,
-                                                   double *__restrict__ zold, int flexible,
-                                                   double *partials) {
-  if (ctl->done) return;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[2] = {0.0, 0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double zi;
-    if (z32) {
-      zi = (double)z32[i];
-      z[i] = zi;
-    } else {
-      zi = z[i];
-    }
-    double ri = r[i];
-    v[0] += ri * zi;
-    if (flexible) {
-      v[1] += ri * (zi - zold[i]);
-      zold[i] = zi;
-    }
-  }
-  block_partials<2>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_rz(PcgCtl *ctl, const double *partials,
-                                                   int nparts, int flexible) {
-  if (ctl->done) return;
-  double tot[2];
-  sum_partials<2>(partials, nparts, tot);
-  if (threadIdx.x == 0) {
-    double rho_new = tot[0];
-    double num = flexible ? tot[1] : rho_new;
-    ctl->beta = num / ctl->rho;
-    ctl->rho = rho_new;
-    if (!(rho_new > 0.0)) ctl->done = 2;
-  }
-}
-void launch_pcg_rz(PcgCtl *ctl, int64_t n, const double *r, double *z, const float *z32,
-                   double *zold, bool flexible, RedBuf rb, hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_pcg_rz<<<grid, kBlock, 0, s>>>(ctl, n, r, z, z32, zold, flexible ? 1 : 0, rb.partials);
-  k_fin_rz<<<1, kBlock, 0, s>>>(ctl, rb.partials, grid, flexible ? 1 : 0);
-}
-
-__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(const PcgCtl *ctl, int64_t n,
-                                                        const double *__restrict__ z,
-                                                        double *__restrict__ p) {
-  if (ctl->done) return;
-  const double beta = ctl->beta;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) p[i] = z[i] + beta * p[i];
-}
-void launch_pcg_pupdate(PcgCtl *ctl, int64_t n, const double *z, double *p, hipStream_t s) {
-  k_pcg_pupdate<<<grid_for(n, kBlock), kBlock, 0, s>>>(ctl, n, z, p);
-}
-
-__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
-                                                const double *__restrict__ b, double *partials) {
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v[0] += a[i] * b[i];
-  block_partials<1>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_store(const double *partials, int nparts,
-                                                      double *out) {
-  double tot[1];
-  sum_partials<1>(partials, nparts, tot);
-  if (threadIdx.x == 0) *out = tot[0];
-}
-void launch_dot(int64_t n, const double *a, const double *b, double *out, RedBuf rb,
-                hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_dot<<<grid, kBlock, 0, s>>>(n, a, b, rb.partials);
-  k_fin_store<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
 }
 
 // ------------------------------------------------------------------ scan
@@ -686,8 +465,6 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
                                    T *, const int *, hipStream_t);                                  \
   template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \
                                   hipStream_t);                                                     \
-  template void launch_dense_apply<T>(int64_t, const double *, const T *, T *, const int *,         \
-                                      hipStream_t);                                                 \
   template void launch_copy_t<T>(int64_t, const T *, T *, const int *, hipStream_t);                \
   template void launch_zero_t<T>(int64_t, T *, const int *, hipStream_t);
 MG_INST(double)

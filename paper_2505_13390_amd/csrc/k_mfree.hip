@@ -170,10 +170,6 @@ static int launch_mf_pass(const MfView<T> &A, In x, Op op, const int *done, doub
 }
 
 template <class T>
-void launch_mf_spmv(const MfView<T> &A, const T *x, T *y, const int *done, hipStream_t s) {
-  launch_mf_pass<T>(A, InVec<T>{x}, OpSpmv<T>{y}, done, nullptr, s);
-}
-template <class T>
 void launch_mf_jacobi(const MfView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                       const int *done, hipStream_t s) {
   const InVec<T> in{zi};
@@ -196,19 +192,10 @@ int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, cons
   return grid;
 }
 
-void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *p, double *q,
-                            double *partials, hipStream_t s) {
-  const int *done = reinterpret_cast<const int *>(ctl);   // PcgCtl::done is the first field
-  const int grid =
-      launch_mf_pass<double>(A, InVec<double>{p}, OpPcgDot{p, q}, done, partials, s);
-  launch_fin_pq(ctl, partials, grid, s);
-}
-
 #define MG_INST(T)                                                                              \
   template void launch_mf_prepare<T>(int64_t, const double *, const double *, const double *,  \
                                      int64_t, const int32_t *, const int8_t *, const double *,  \
                                      T *, T *, hipStream_t);                                    \
-  template void launch_mf_spmv<T>(const MfView<T> &, const T *, T *, const int *, hipStream_t); \
   template void launch_mf_jacobi<T>(const MfView<T> &, const T *, const T *, const T *, T *,    \
                                     const int *, hipStream_t);                                  \
   template void launch_mf_residual<T>(const MfView<T> &, const T *, const T *, T *,             \

@@ -107,17 +107,6 @@ void launch_strong(const CsrView<double> &A, const double *diag, double theta2, 
 // ------------------------------------------------------------ MIS-2
 constexpr uint64_t kRootKey = ~0ULL;
 
-__global__ void k_mis_init(int64_t n, const uint8_t *__restrict__ conn, uint64_t salt, int level,
-                           uint64_t *__restrict__ key) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  key[i] = conn[i] ? prio_key(salt, level, i) + 1ULL : 0ULL;
-}
-void launch_mis_init(int64_t n, const uint8_t *conn, uint64_t salt, int level, uint64_t *key,
-                     hipStream_t s) {
-  if (n) k_mis_init<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, conn, salt, level, key);
-}
-
 // m1[i] = max of key over i and its strong neighbours
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_mis_max1(int64_t n, const int64_t *__restrict__ rp,
@@ -328,14 +317,6 @@ void launch_sort_segments(int64_t nseg, const int64_t *ptr, int32_t *mem, hipStr
 // ------------------------------------------------------------ colouring
 constexpr int kMaxColors = 256;
 
-__global__ void k_color_keys(int64_t n, uint64_t salt, uint64_t *__restrict__ key) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) key[i] = prio_key(salt, 0, i);
-}
-void launch_color_keys(int64_t n, uint64_t salt, uint64_t *key, hipStream_t s) {
-  if (n) k_color_keys<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, salt, key);
-}
-
 // Jones-Plassmann colouring driven by counters: cnt[i] = number of
 // neighbours with a higher key; a row is coloured once that count reaches
 // zero (all higher-priority neighbours coloured), with the smallest colour
@@ -484,35 +465,6 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int64_t cnt, const int32_t 
 void launch_gs_color(int64_t cnt, const int32_t *rows, const CsrView<double> &A,
                      const double *diag, double *x, hipStream_t s) {
   if (cnt) k_gs_color<<<blocks_for(cnt, kBlock), kBlock, 0, s>>>(cnt, rows, A.rowptr, A.col, A.val, diag, x);
-}
-
-// max |a| over all stored entries: non-negative doubles order like their bits
-__global__ __launch_bounds__(kBlock) void k_absmax(int64_t nnz, const double *__restrict__ val,
-                                                   unsigned long long *out) {
-  int64_t lo, hi;
-  block_range(nnz, lo, hi);
-  unsigned long long m = 0;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(val[e]));
-    m = b > m ? b : m;
-  }
-  m = group_max_u64<kWave>(m);
-  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
-}
-void launch_absmax(int64_t nnz, const double *val, unsigned long long *out, hipStream_t s) {
-  if (nnz) k_absmax<<<grid_for(nnz, kBlock), kBlock, 0, s>>>(nnz, val, out);
-}
-
-__global__ void k_candidate_init(int64_t n, uint64_t salt, const unsigned long long *amax,
-                                 double *__restrict__ B) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double am = __longlong_as_double((long long)*amax);
-  B[i] = uniform_open(mix64_salted(salt, (uint64_t)i)) * am;
-}
-void launch_candidate_init(int64_t n, uint64_t salt, const unsigned long long *amax, double *B,
-                           hipStream_t s) {
-  if (n) k_candidate_init<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, salt, amax, B);
 }
 
 __global__ void k_normalize(int64_t na, const int64_t *__restrict__ ap,
@@ -802,79 +754,6 @@ void launch_gal_numeric(int64_t nnzc, const int32_t *crow, const int32_t *ccol,
   if (nnzc)
     k_gal_numeric<<<blocks_for(nnzc, kBlock), kBlock, 0, s>>>(nnzc, crow, ccol, mirror, gl_ptr, gl_idx,
                                                               gl_row, fcol, fval, p, cval, cval32);
-}
-
-// ------------------------------------------------------------ power method
-__global__ void k_pow_init(int64_t n, uint64_t salt, int level, double *__restrict__ v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = uniform_open(mix64_salted(salt, ((uint64_t)level << 40) + (uint64_t)i));
-}
-void launch_pow_init(int64_t n, uint64_t salt, int level, double *v, hipStream_t s) {
-  if (n) k_pow_init<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, salt, level, v);
-}
-__global__ __launch_bounds__(kBlock) void k_pow_scale(int64_t n, double *__restrict__ w,
-                                                      const double *__restrict__ diag,
-                                                      double *partials) {
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double v[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double wi = w[i] / diag[i];
-    w[i] = wi;
-    v[0] += wi * wi;
-  }
-  block_partials<1>(v, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_store1(const double *partials, int nparts,
-                                                       double *out) {
-  double tot[1];
-  sum_partials<1>(partials, nparts, tot);
-  if (threadIdx.x == 0) *out = tot[0];
-}
-void launch_pow_scale(int64_t n, double *w, const double *diag, double *out, RedBuf rb,
-                      hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_pow_scale<<<grid, kBlock, 0, s>>>(n, w, diag, rb.partials);
-  k_fin_store1<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
-}
-__global__ void k_pow_normalize(int64_t n, const double *__restrict__ w, const double *nrm2,
-                                double *__restrict__ v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double nr = sqrt(*nrm2);
-  if (i < n && nr > 0.0) v[i] = w[i] / nr;
-}
-void launch_pow_normalize(int64_t n, const double *w, const double *nrm2, double *v,
-                          hipStream_t s) {
-  if (n) k_pow_normalize<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, w, nrm2, v);
-}
-__global__ __launch_bounds__(kBlock) void k_rayleigh(int64_t n, const double *__restrict__ v,
-                                                     const double *__restrict__ Av,
-                                                     const double *__restrict__ diag,
-                                                     double *partials) {
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  double s[2] = {0.0, 0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double vi = v[i];
-    s[0] += vi * Av[i];
-    s[1] += vi * diag[i] * vi;
-  }
-  block_partials<2>(s, partials);
-}
-__global__ __launch_bounds__(kBlock) void k_fin_store2(const double *partials, int nparts,
-                                                       double *out) {
-  double tot[2];
-  sum_partials<2>(partials, nparts, tot);
-  if (threadIdx.x == 0) {
-    out[0] = tot[0];
-    out[1] = tot[1];
-  }
-}
-void launch_rayleigh(int64_t n, const double *v, const double *Av, const double *diag,
-                     double *out, RedBuf rb, hipStream_t s) {
-  int grid = grid_for(n, kBlock);
-  k_rayleigh<<<grid, kBlock, 0, s>>>(n, v, Av, diag, rb.partials);
-  k_fin_store2<<<1, kBlock, 0, s>>>(rb.partials, grid, out);
 }
 
 }  // namespace mgpbd

@@ -57,9 +57,7 @@ template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
 // z_i += p_i ec[agg_i]
 template <class T> void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec,
                                        T *z, const int *done, hipStream_t s);
-// ec = Ainv rc (FP64 dense, n <= dense_max)
-template <class T> void launch_dense_apply(int64_t n, const double *Ainv, const T *rc, T *ec,
-                                           const int *done, hipStream_t s);
+
 
 void launch_d2f(int64_t n, const double *in, float *out, const int *done, hipStream_t s);
 void launch_f2d(int64_t n, const float *in, double *out, const int *done, hipStream_t s);
@@ -71,29 +69,8 @@ void launch_fill_i32(int64_t n, int32_t v, int32_t *out, hipStream_t s);
 void launch_fill_u8(int64_t n, uint8_t v, uint8_t *out, hipStream_t s);
 
 // ---------------- PCG (FP64 outer loop), control block in device memory ----
-struct RedBuf {  // partial sums + ticket for grid_reduce (up to 2 values)
-  double *partials = nullptr;
-  unsigned *ticket = nullptr;
-};
-void launch_pcg_init(PcgCtl *ctl, int64_t n, const double *b, double *x, double *r, RedBuf rb,
-                     hipStream_t s);
-void launch_pcg_init_p(PcgCtl *ctl, int64_t n, const double *r, const double *z, double *p,
-                       double *zold, bool flexible, RedBuf rb, hipStream_t s);
 // finisher of p^T A p: pq, alpha (or breakdown) from nparts block partials
 void launch_fin_pq(PcgCtl *ctl, const double *partials, int nparts, hipStream_t s);
-void launch_pcg_spmv_dot(PcgCtl *ctl, const CsrView<double> &A, const double *p, double *q,
-                         RedBuf rb, hipStream_t s);
-void launch_pcg_update(PcgCtl *ctl, int64_t n, const double *p, const double *q, double *x,
-                       double *r, RedBuf rb, hipStream_t s);
-// rho_new = r^T z (flexible: beta numerator r^T (z - zold), zold <- z); z32 != nullptr:
-// z = (double) z32 first (mixed precision V-cycle output)
-void launch_pcg_rz(PcgCtl *ctl, int64_t n, const double *r, double *z, const float *z32,
-                   double *zold, bool flexible, RedBuf rb, hipStream_t s);
-void launch_pcg_pupdate(PcgCtl *ctl, int64_t n, const double *z, double *p, hipStream_t s);
-
-// generic deterministic reductions into a device scalar
-void launch_dot(int64_t n, const double *a, const double *b, double *out, RedBuf rb,
-                hipStream_t s);
 
 // ---------------- scans (deterministic) ----------------
 // out[i] = sum_{k<i} in[k], out[n] = total (out has n+1 entries)

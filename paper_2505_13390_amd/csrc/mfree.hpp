@@ -40,19 +40,14 @@ void launch_mf_prepare(int64_t nv, const double *x, const double *y, const doubl
                        const double *grad, T *pos, T *gT, hipStream_t s);
 
 template <class T>
-void launch_mf_spmv(const MfView<T> &A, const T *x, T *y, const int *done, hipStream_t s);
-template <class T>
 void launch_mf_jacobi(const MfView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                       const int *done, hipStream_t s);
 template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s);
-// q = A p and the PCG step length (one control block)
-void launch_mf_pcg_spmv_dot(PcgCtl *ctl, const MfView<double> &A, const double *p, double *q,
-                            double *partials, hipStream_t s);
-// the two kernels of that product on their own (for per-kernel timing):
-// the vertex gather, then the row pass writing q and the partial sums of
-// p^T q (returns the number of partials; launch_fin_pq finishes)
+// the PCG product q = A p as its two kernels (timed one by one when
+// profiling): the vertex gather, then the row pass writing q and the partial
+// sums of p^T q (returns the number of partials; launch_fin_pq finishes)
 void launch_mf_gather(const MfView<double> &A, const double *x, const int *done, hipStream_t s);
 int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, const int *done,
                        double *partials, hipStream_t s);

@@ -15,9 +15,6 @@ void launch_extract_diag(int64_t n, const int64_t *dpos, const double *val, doub
 // strength of connection, kept iff a_ij^2 >= theta2 (|a_ii| |a_jj|), j != i
 void launch_strong(const CsrView<double> &A, const double *diag, double theta2, uint8_t *strong,
                    uint8_t *conn, hipStream_t s);
-// aggregation key: 0 for isolated rows, 1 + priority for the others
-void launch_mis_init(int64_t n, const uint8_t *conn, uint64_t salt, int level, uint64_t *key,
-                     hipStream_t s);
 void launch_mis_round(const CsrView<double> &A, const uint8_t *strong, uint64_t *key,
                       uint64_t *m1, int *undecided, hipStream_t s);
 void launch_root_flags(int64_t n, const uint64_t *key, int32_t *flag, hipStream_t s);
@@ -30,8 +27,6 @@ void launch_scatter_members(int64_t n, const int32_t *agg, const int64_t *ptr, i
                             int32_t *mem, hipStream_t s);
 void launch_sort_segments(int64_t nseg, const int64_t *ptr, int32_t *mem, hipStream_t s);
 
-// Jones-Plassmann greedy colouring over the structural graph
-void launch_color_keys(int64_t n, uint64_t salt, uint64_t *key, hipStream_t s);
 // Jones-Plassmann by counters: higher-key neighbour counts and the first
 // frontier (rows with none), then one launch per frontier
 void launch_color_count(const CsrView<double> &A, const uint64_t *key, int32_t *cnt,
@@ -45,9 +40,6 @@ void launch_scatter_colors(int64_t n, const int32_t *color, const int64_t *off, 
 // one colour of a Gauss-Seidel sweep on A x = 0
 void launch_gs_color(int64_t cnt, const int32_t *rows, const CsrView<double> &A,
                      const double *diag, double *x, hipStream_t s);
-void launch_absmax(int64_t nnz, const double *val, unsigned long long *out, hipStream_t s);
-void launch_candidate_init(int64_t n, uint64_t salt, const unsigned long long *amax, double *B,
-                           hipStream_t s);
 // one-column QR per aggregate: p = B / |B|_aggregate, Bn = |B|_aggregate
 void launch_normalize(int64_t na, const int64_t *ap, const int32_t *mem, const double *B,
                       double *p, float *p32, double *Bn, hipStream_t s);
@@ -67,24 +59,5 @@ void launch_gal_numeric(int64_t nnzc, const int32_t *crow, const int32_t *ccol,
                         const int32_t *mirror, const int64_t *gl_ptr, const int32_t *gl_idx,
                         const int32_t *gl_row, const int32_t *fcol, const double *fval,
                         const double *p, double *cval, float *cval32, hipStream_t s);
-
-// power method on D^-1 A
-void launch_pow_init(int64_t n, uint64_t salt, int level, double *v, hipStream_t s);
-// w_i = w_i / diag_i, out = sum w_i^2
-void launch_pow_scale(int64_t n, double *w, const double *diag, double *out, RedBuf rb,
-                      hipStream_t s);
-// v = w / sqrt(*nrm2) when *nrm2 > 0
-void launch_pow_normalize(int64_t n, const double *w, const double *nrm2, double *v,
-                          hipStream_t s);
-// out[0] = v^T Av, out[1] = sum (v_i diag_i) v_i
-void launch_rayleigh(int64_t n, const double *v, const double *Av, const double *diag,
-                     double *out, RedBuf rb, hipStream_t s);
-
-// dense coarsest level
-void launch_csr_to_dense(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
-                         double *D, hipStream_t s);
-// in-place Cholesky of D (lower) and Ainv = D^-1; status = 1 on a pivot <= 0
-void launch_chol_inverse(int64_t n, double *D, double *Y, double *Ainv, int *status,
-                         hipStream_t s);
 
 }  // namespace mgpbd
