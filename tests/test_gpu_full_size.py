@@ -1,9 +1,11 @@
-"""Parity at the full size of the 32x32x128 beam (1,731,776 rows, 155,246,662
-entries), in the configuration bench.py times: the first global iteration of
-frame 0. Checked element by element where the oracle can compute the whole
-result (assembly of A and b, the complete AMG hierarchy of that A), and by
-properties that hold at any size elsewhere (true residual of the PCG solve,
-agreement of the matrix-free and assembled fine operators)."""
+"""Parity at full size, in the configurations bench.py times: the first
+global iteration of frame 0 of the 32x32x128 beam (1,731,776 rows,
+155,246,662 entries; FP64 and FP32 V-cycle) and of the 64-beam batch
+(12,619,205 rows). Checked element by element where the oracle can compute
+the whole result (assembly of A and b, the complete AMG hierarchy of that A,
+the smallest bodies of the batch), and by properties that hold at any size
+elsewhere (true residual of the PCG solve, agreement of the matrix-free and
+assembled fine operators, of the two precisions)."""
 import numpy as np
 import pytest
 
@@ -110,3 +112,60 @@ def test_c1_matrix_free_matches_assembled(c1):
     csr.close()
     assert abs(int(res["pcg_iters"][0]) - int(rc["pcg_iters"][0])) <= 0.05 * rc["pcg_iters"][0]
     assert err <= 1e-9
+
+
+def test_c1_mixed_precision_true_residual():
+    """FP32 V-cycle at full size: the outer FP64 PCG still reaches 1e-6 on the
+    FP64 system (true residual), and positions stay within 1e-7 of FP64."""
+    import scipy.sparse as sp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = W.beam_c1()
+    _, go = opts(precision=B.PREC_MIXED)
+    body = B.Body(w, go)
+    res = body.step(1)
+    rp, col, val = B.mgpbd_get_matrix(body.ctx, 0)
+    A = sp.csr_matrix((val, col, rp))
+    m = rp.size - 1
+    b = B.mgpbd_get_rhs(body.ctx, m)
+    x = B.mgpbd_get_lambda(body.ctx, m)
+    rel = float(np.linalg.norm(A @ x - b) / np.linalg.norm(b))
+    log("C1 mixed: pcg iters %d, recurrence %.3e, true residual %.3e"
+        % (res["pcg_iters"][0], res["pcg_ratio"][0], rel))
+    _, g64 = opts()
+    ref = B.Body(w, g64)
+    ref.step(1)
+    err = rel_pos_err(body.positions(), ref.positions())
+    log("C1 mixed vs FP64 position difference %.3e" % err)
+    body.close()
+    ref.close()
+    assert res["pcg_ratio"][0] <= 1e-6
+    assert rel <= 1.5e-6
+    assert err <= 1e-7
+
+
+def test_c3_batch_full_size():
+    """The 64-beam batch (12.6M rows) as bench.py runs it (one system, FP32
+    V-cycle): every body's solve reaches 1e-6, and the smallest bodies match
+    their own FP64 oracle runs within the mixed-precision bound."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ws = W.batch_c3()
+    oo, go = opts(precision=B.PREC_MIXED)
+    oo64, _ = opts()
+    batch = B.Batch(ws, go)
+    res = batch.step(1)
+    iters = [int(r["pcg_iters"][0]) for r in res]
+    log("C3 batch: %d bodies, %d rows, PCG iterations %d..%d"
+        % (len(ws), sum(w.n_rows for w in ws), min(iters), max(iters)))
+    for r in res:
+        assert r["pcg_ratio"][0] <= 1e-6
+    small = sorted(range(len(ws)), key=lambda k: ws[k].n_rows)[:3]
+    for k in small:
+        sim = O.Sim(ws[k], oo64)
+        pos, vel = O.positions(ws[k])
+        sim.step(pos, vel, 1)
+        err = rel_pos_err(batch.bodies[k].positions(), pos)
+        log("  body %d (%d rows): position error vs FP64 oracle %.3e" % (k, ws[k].n_rows, err))
+        assert err <= 1e-7
+    batch.close()
