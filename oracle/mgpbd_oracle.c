@@ -32,6 +32,10 @@
  *  - Sec. 4.5: omega-Jacobi smoother, 2 pre + 2 post sweeps,
  *    omega = 2 / (lambda_max(D^-1 A) + lambda_min), lambda_max by the power
  *    method, lambda_min a user estimate (0.1); computed at setup only.
+ *    Optionally the Chebyshev smoother of the same subsection: s steps of
+ *    Chebyshev acceleration of Jacobi on the interval [lambda_min, lambda_max]
+ *    (the recurrence of Saad, Iterative Methods for Sparse Linear Systems,
+ *    2nd ed., Alg. 12.1, with M = D), coefficients fixed at setup.
  *
  * Readings where the paper is silent (each listed in the design notes):
  *  - one near-kernel candidate per aggregate (K = 1): P column = candidate
@@ -77,6 +81,7 @@ typedef struct orc_opts {
   double eps_b;        /* stop the frame loop when |b| < eps_b (0 = never) */
   int flexible;        /* 0 = Fletcher-Reeves beta, 1 = Polak-Ribiere beta */
   double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 */
+  int smoother;        /* 0 = omega-Jacobi, 1 = Chebyshev (Sec. 4.5): 0 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -98,6 +103,7 @@ void orc_default_opts(orc_opts *o) {
   o->eps_b = 0.0;
   o->flexible = 0;
   o->lmax_scale = 1.05;
+  o->smoother = 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -458,6 +464,7 @@ typedef struct {
   csr A;
   double *diag;       /* A_ii */
   double omega;       /* Jacobi weight */
+  double lmax;        /* lmax_scale * power-method estimate of lambda_max(D^-1 A) */
   /* transfer to level l+1 (absent on the last level) */
   int32_t *agg;       /* aggregate of each row, -1 = isolated */
   int64_t n_agg;
@@ -477,7 +484,7 @@ typedef struct {
   int64_t nd;
   orc_opts o;
   /* scratch per level */
-  double *tmp[32], *res[32], *rc[32], *zc[32];
+  double *tmp[32], *res[32], *rc[32], *zc[32], *dir[32];
 } hier_t;
 
 static void level_free(level_t *lv) {
@@ -491,7 +498,7 @@ void orc_hier_free(hier_t *h) {
   if (!h) return;
   for (int l = 0; l < h->L; ++l) {
     level_free(&h->lev[l]);
-    free(h->tmp[l]); free(h->res[l]); free(h->rc[l]); free(h->zc[l]);
+    free(h->tmp[l]); free(h->res[l]); free(h->rc[l]); free(h->zc[l]); free(h->dir[l]);
   }
   free(h->chol);
   free(h);
@@ -791,15 +798,16 @@ static int finish_level(hier_t *h, int l) {
   h->res[l] = malloc(sizeof(double) * (nl ? nl : 1));
   h->rc[l] = malloc(sizeof(double) * (nl ? nl : 1));
   h->zc[l] = malloc(sizeof(double) * (nl ? nl : 1));
-  if (!lv->diag || !h->tmp[l] || !h->res[l] || !h->rc[l] || !h->zc[l]) return ORC_E_NOMEM;
+  h->dir[l] = malloc(sizeof(double) * (nl ? nl : 1));
+  if (!lv->diag || !h->tmp[l] || !h->res[l] || !h->rc[l] || !h->zc[l] || !h->dir[l])
+    return ORC_E_NOMEM;
   for (int64_t i = 0; i < nl; ++i) {
     lv->diag[i] = csr_get_diag(&lv->A, i);
     if (!(lv->diag[i] > 0.0)) return ORC_E_BREAKDOWN;
   }
-  lv->omega = nl ? 2.0 / (h->o.lmax_scale *
-                              power_lmax(&lv->A, lv->diag, h->o.power_iters, h->o.seed, l) +
-                          h->o.lambda_min)
-                 : 0.0;
+  lv->lmax = nl ? h->o.lmax_scale * power_lmax(&lv->A, lv->diag, h->o.power_iters, h->o.seed, l)
+               : 0.0;
+  lv->omega = nl ? 2.0 / (lv->lmax + h->o.lambda_min) : 0.0;
   return ORC_OK;
 }
 
@@ -934,18 +942,64 @@ int orc_hier_refresh(hier_t *h, const double *val0) {
   return ORC_OK;
 }
 
-/* one V-cycle z = V(l, r): Jacobi pre-sweeps (the first from z = 0),
-   residual, restriction P^T, coarse correction, prolongation, post-sweeps */
+/* Chebyshev smoothing on level l: `steps` steps of Chebyshev acceleration of
+   Jacobi for A z = r on the eigenvalue interval [a, b] = [lambda_min, lmax]
+   of D^-1 A: theta = (b + a)/2, delta = (b - a)/2, sigma = theta/delta,
+   rho_0 = 1/sigma, d_0 = (1/theta) D^-1 (r - A z_0), z_1 = z_0 + d_0, and for
+   k >= 1: rho_k = 1/(2 sigma - rho_{k-1}),
+   d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) D^-1 (r - A z_k),
+   z_{k+1} = z_k + d_k. from_zero: z_0 = 0 (no product in the first step). */
+static void cheb_smooth(hier_t *h, int l, const double *r, double *z, int steps, int from_zero) {
+  level_t *lv = &h->lev[l];
+  int64_t n = lv->A.n;
+  double *t = h->tmp[l], *d = h->dir[l];
+  double a = h->o.lambda_min, b = lv->lmax;
+  double theta = (b + a) / 2.0, delta = (b - a) / 2.0, sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < steps; ++k) {
+    double c1 = 0.0, c2 = 1.0 / theta;
+    if (k > 0) {
+      double rho_new = 1.0 / (2.0 * sigma - rho);
+      c1 = rho_new * rho;
+      c2 = 2.0 * rho_new / delta;
+      rho = rho_new;
+    }
+    if (k == 0 && from_zero) {
+      for (int64_t i = 0; i < n; ++i) {
+        d[i] = c2 * (r[i] / lv->diag[i]);
+        z[i] = d[i];
+      }
+      continue;
+    }
+    spmv(&lv->A, z, t);
+    for (int64_t i = 0; i < n; ++i) {
+      double ri = (r[i] - t[i]) / lv->diag[i];
+      d[i] = (k == 0) ? c2 * ri : c1 * d[i] + c2 * ri;
+      z[i] = z[i] + d[i];
+    }
+  }
+}
+
+/* one V-cycle z = V(l, r): pre-smoothing from z = 0, residual, restriction
+   P^T, coarse correction, prolongation, post-smoothing; Jacobi sweeps or
+   Chebyshev steps */
 static void vcycle(hier_t *h, int l, const double *r, double *z) {
   level_t *lv = &h->lev[l];
   int64_t n = lv->A.n;
   if (l == h->L - 1 && h->last_dense) { chol_solve(h, r, z); return; }
   double om = lv->omega;
   double *t = h->tmp[l];
-  for (int64_t i = 0; i < n; ++i) z[i] = om * (r[i] / lv->diag[i]);
-  for (int s = 1; s < h->o.pre_sweeps; ++s) {
-    spmv(&lv->A, z, t);
-    for (int64_t i = 0; i < n; ++i) z[i] = z[i] + om * ((r[i] - t[i]) / lv->diag[i]);
+  const int cheb = h->o.smoother == 1;
+  if (h->o.pre_sweeps == 0) {
+    for (int64_t i = 0; i < n; ++i) z[i] = 0.0;
+  } else if (cheb) {
+    cheb_smooth(h, l, r, z, h->o.pre_sweeps, 1);
+  } else {
+    for (int64_t i = 0; i < n; ++i) z[i] = om * (r[i] / lv->diag[i]);
+    for (int s = 1; s < h->o.pre_sweeps; ++s) {
+      spmv(&lv->A, z, t);
+      for (int64_t i = 0; i < n; ++i) z[i] = z[i] + om * ((r[i] - t[i]) / lv->diag[i]);
+    }
   }
   if (l + 1 < h->L) {
     double *res = h->res[l];
@@ -965,9 +1019,13 @@ static void vcycle(hier_t *h, int l, const double *r, double *z) {
     for (int64_t i = 0; i < n; ++i)
       if (lv->agg[i] >= 0) z[i] = z[i] + lv->p[i] * zc[lv->agg[i]];
   }
-  for (int s = 0; s < h->o.post_sweeps; ++s) {
-    spmv(&lv->A, z, t);
-    for (int64_t i = 0; i < n; ++i) z[i] = z[i] + om * ((r[i] - t[i]) / lv->diag[i]);
+  if (cheb) {
+    cheb_smooth(h, l, r, z, h->o.post_sweeps, 0);
+  } else {
+    for (int s = 0; s < h->o.post_sweeps; ++s) {
+      spmv(&lv->A, z, t);
+      for (int64_t i = 0; i < n; ++i) z[i] = z[i] + om * ((r[i] - t[i]) / lv->diag[i]);
+    }
   }
 }
 

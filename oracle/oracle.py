@@ -33,7 +33,8 @@ class Opts(C.Structure):
                 ("dense_max", C.c_int), ("max_levels", C.c_int), ("power_iters", C.c_int),
                 ("omega_relax", C.c_double), ("tol", C.c_double), ("max_pcg", C.c_int),
                 ("seed", C.c_uint64), ("reuse_interval", C.c_int), ("b_mode", C.c_int),
-                ("eps_b", C.c_double), ("flexible", C.c_int), ("lmax_scale", C.c_double)]
+                ("eps_b", C.c_double), ("flexible", C.c_int), ("lmax_scale", C.c_double),
+                ("smoother", C.c_int)]
 
 
 _lib = None

@@ -584,3 +584,105 @@ def test_indefinite_matrix_breaks_down():
     assert st["status"] == O.E_BREAKDOWN
     with pytest.raises(O.OracleError):
         O.Hier.build(A.indptr.astype(np.int64), A.indices, A.data)  # dense factor fails
+
+
+# ---------------------------------------------------------------- smoothers
+def unit_diag_spd(n, rng, spread=0.45):
+    """A = D^1/2 S D^1/2 with S symmetric, unit diagonal and positive
+    definite, D > 0: diag(A) = D and D^-1 A is similar to S."""
+    E = rng.uniform(-1.0, 1.0, (n, n))
+    E = (E + E.T) / 2.0
+    np.fill_diagonal(E, 0.0)
+    E *= spread / np.abs(np.linalg.eigvalsh(E)).max()
+    S = np.eye(n) + E
+    d = rng.uniform(0.5, 4.0, n)
+    A = np.sqrt(d)[:, None] * S * np.sqrt(d)[None, :]
+    return A, S, d
+
+
+def one_level_smoother_hier(A, **kw):
+    """A hierarchy with one level solved by smoothing only (no dense solve),
+    so one V-cycle is pre-smoothing from zero followed by post-smoothing."""
+    As = sp.csr_matrix(A)
+    As.sort_indices()
+    o = O.default_opts(max_levels=1, dense_max=0, **kw)
+    h = O.Hier.build(As.indptr.astype(np.int64), As.indices, As.data, o)
+    assert h.levels == 1 and not h.last_dense
+    return h, o
+
+
+def test_chebyshev_smoother_error_is_the_chebyshev_polynomial():
+    """Sec. 4.5, Chebyshev smoother: k steps on [a, b] = [lambda_min, lmax]
+    reduce each eigencomponent of the error by T_k((theta - lam)/delta) /
+    T_k(theta/delta) (Saad, Alg. 12.1, with M = D); one V-cycle of a one-level
+    hierarchy applies it before and after, so the error of V r against A^-1 r
+    is that ratio squared. The polynomials come from numpy's Chebyshev series,
+    not from the recurrence."""
+    rng = np.random.default_rng(21)
+    n = 14
+    A, S, d = unit_diag_spd(n, rng)
+    lam, Q = np.linalg.eigh(S)
+    for k in (1, 2, 3):
+        h, o = one_level_smoother_hier(A, smoother=1, pre_sweeps=k, post_sweeps=k)
+        lmax = 2.0 / h.info(0)["omega"] - o.lambda_min
+        a, b = o.lambda_min, lmax
+        theta, delta = (b + a) / 2.0, (b - a) / 2.0
+        Tk = lambda x: np.polynomial.chebyshev.chebval(x, [0.0] * k + [1.0])
+        R = Tk((theta - lam) / delta) / Tk(theta / delta)
+        r = rng.standard_normal(n)
+        xs = np.linalg.solve(A, r)
+        e = xs - h.vcycle(r)
+        # D^-1 A = D^-1/2 S D^1/2: eigenvectors D^-1/2 Q
+        Dh = np.sqrt(d)
+        e_ref = (Q @ (R ** 2 * (Q.T @ (Dh * xs)))) / Dh
+        assert np.abs(e - e_ref).max() <= 1e-11 * np.abs(xs).max(), k
+
+
+def test_chebyshev_one_step_is_weighted_jacobi():
+    """A single Chebyshev step from zero is the omega-Jacobi sweep with
+    omega = 2 / (a + b), the weight Sec. 4.5 gives for Jacobi."""
+    rng = np.random.default_rng(22)
+    A, S, d = unit_diag_spd(10, rng)
+    hc, _ = one_level_smoother_hier(A, smoother=1, pre_sweeps=1, post_sweeps=1)
+    hj, _ = one_level_smoother_hier(A, smoother=0, pre_sweeps=1, post_sweeps=1)
+    r = rng.standard_normal(10)
+    zc, zj = hc.vcycle(r), hj.vcycle(r)
+    assert np.abs(zc - zj).max() <= 1e-14 * np.abs(zj).max()
+
+
+def test_jacobi_smoother_error_is_the_jacobi_polynomial():
+    """omega-Jacobi with s sweeps reduces each eigencomponent of D^-1 A by
+    (1 - omega lam)^s; pre and post: squared."""
+    rng = np.random.default_rng(23)
+    n = 12
+    A, S, d = unit_diag_spd(n, rng)
+    lam, Q = np.linalg.eigh(S)
+    for s_ in (1, 2):
+        h, o = one_level_smoother_hier(A, smoother=0, pre_sweeps=s_, post_sweeps=s_)
+        om = h.info(0)["omega"]
+        r = rng.standard_normal(n)
+        xs = np.linalg.solve(A, r)
+        e = xs - h.vcycle(r)
+        Dh = np.sqrt(d)
+        e_ref = (Q @ ((1.0 - om * lam) ** (2 * s_) * (Q.T @ (Dh * xs)))) / Dh
+        assert np.abs(e - e_ref).max() <= 1e-11 * np.abs(xs).max(), s_
+
+
+def test_zero_sweeps_leave_only_the_coarse_correction():
+    """pre = post = 0 on a one-level smoothing-only hierarchy: V r = 0."""
+    rng = np.random.default_rng(24)
+    A, S, d = unit_diag_spd(8, rng)
+    h, _ = one_level_smoother_hier(A, pre_sweeps=0, post_sweeps=0)
+    assert not np.any(h.vcycle(rng.standard_normal(8)))
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_vcycle_symmetric_positive_both_smoothers(smoother):
+    w, s, rp, col, val, b, h = small_hier(smoother=smoother)
+    assert h.levels >= 2
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        y, z = rng.standard_normal((2, s.m))
+        a1, a2 = z @ h.vcycle(y), y @ h.vcycle(z)
+        assert abs(a1 - a2) <= 1e-12 * (abs(a1) + abs(a2))
+        assert y @ h.vcycle(y) > 0
