@@ -109,7 +109,8 @@ def bench_batch(args, B, W):
     n_iters = args.iters or ws[0].iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
-                                  matrix_free=1 if args.fine == "mf" else 0)
+                                  matrix_free=1 if args.fine == "mf" else 0,
+                                  smoother=1 if args.smoother == "chebyshev" else 0)
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
     rows = [w.n_rows for w in ws]
@@ -172,6 +173,8 @@ def main():
     ap.add_argument("--max-pcg", type=int, default=None)
     ap.add_argument("--fine", default="mf", choices=["mf", "csr"],
                     help="fine-level products: matrix-free (default) or assembled CSR")
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev"],
+                    help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default) or Chebyshev")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -201,7 +204,8 @@ def main():
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   profile_spmv=0 if args.no_profile else 1,
-                                  matrix_free=1 if args.fine == "mf" else 0)
+                                  matrix_free=1 if args.fine == "mf" else 0,
+                                  smoother=1 if args.smoother == "chebyshev" else 0)
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
     t0 = time.perf_counter()
@@ -267,7 +271,7 @@ def main():
         "config": {"workload": w.name, "rows": body.m, "nnz": body.nnz,
                    "iters_per_frame": n_iters, "precision": args.precision,
                    "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
-                   "reuse_interval": args.reuse, "tol": 1e-6,
+                   "smoother": args.smoother, "reuse_interval": args.reuse, "tol": 1e-6,
                    "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
                    "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps},

@@ -88,6 +88,10 @@ typedef struct {
                            assembled A still feeds the setup, the Galerkin products and
                            the Jacobi diagonal); 0: assembled CSR. Simulation contexts
                            only; mgpbd_solve always uses the caller's CSR: 1 */
+  int32_t smoother;     /* V-cycle smoother (Sec. 4.5): 0 = omega-Jacobi, 1 = Chebyshev
+                           (pre_sweeps / post_sweeps steps of Chebyshev acceleration of
+                           Jacobi on [lambda_min, lmax_scale * lambda_max] of D^-1 A,
+                           coefficients fixed at setup): 0 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.

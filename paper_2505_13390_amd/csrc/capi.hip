@@ -109,6 +109,8 @@ void check_options(const mgpbd_options &o) {
              MGPBD_E_INVALID_ARG, "spmv_lanes must be 0, 4, 8, 16, 32 or 64");
   MG_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, MGPBD_E_INVALID_ARG,
              "matrix_free must be 0 or 1");
+  MG_REQUIRE(o.smoother == 0 || o.smoother == 1, MGPBD_E_INVALID_ARG,
+             "smoother must be 0 (omega-Jacobi) or 1 (Chebyshev)");
 }
 
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
@@ -304,6 +306,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->spmv_tile = 0;
   o->spmv_lanes = 0;
   o->matrix_free = 1;
+  o->smoother = 0;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {

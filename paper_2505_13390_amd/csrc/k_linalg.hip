@@ -202,6 +202,41 @@ void launch_jacobi_scaled(const CsrView<T> &A, const T *wdinv, const T *r, T *zo
   const InScaled<T> in{r, wdinv};
   launch_pass<T>(A, in, OpJacobi<T, InScaled<T>>{wdinv, r, in, zo}, done, nullptr, s);
 }
+// first Chebyshev step from z = 0: d = c2 D^-1 r, z = d
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t n, const T *__restrict__ r,
+                                                       const T *__restrict__ dinv,
+                                                       const T *__restrict__ coef,
+                                                       const int32_t *__restrict__ rowseg,
+                                                       int steps, T *__restrict__ d,
+                                                       T *__restrict__ z, const int *done) {
+  if (done && *done) return;
+  int64_t lo, hi;
+  block_range(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const T c2 = coef[2 * (int64_t)(rowseg ? rowseg[i] : 0) * steps + 1];
+    const T dn = c2 * (r[i] * dinv[i]);
+    d[i] = dn;
+    z[i] = dn;
+  }
+}
+template <class T>
+void launch_cheb_first(int64_t n, const T *r, const T *dinv, const T *coef,
+                       const int32_t *rowseg, int steps, T *d, T *z, const int *done,
+                       hipStream_t s) {
+  if (n == 0) return;
+  k_cheb_first<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, r, dinv, coef, rowseg, steps, d, z,
+                                                         done);
+}
+template <class T>
+void launch_cheb(const CsrView<T> &A, const T *r, const T *dinv, const T *coef,
+                 const int32_t *rowseg, int steps, int k, const T *zi, T *d, T *zo,
+                 const int *done, hipStream_t s) {
+  const InVec<T> in{zi};
+  launch_pass<T>(A, in, OpCheb<T, InVec<T>>{r, dinv, d, zo, coef, rowseg, steps, k, in}, done,
+                 nullptr, s);
+}
+
 template <class T>
 void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
                      hipStream_t s) {
@@ -461,6 +496,10 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
                                    hipStream_t);                                                    \
   template void launch_jacobi_scaled<T>(const CsrView<T> &, const T *, const T *, T *, const int *, \
                                         hipStream_t);                                               \
+  template void launch_cheb_first<T>(int64_t, const T *, const T *, const T *, const int32_t *, int, \
+                                     T *, T *, const int *, hipStream_t);                           \
+  template void launch_cheb<T>(const CsrView<T> &, const T *, const T *, const T *, const int32_t *, \
+                               int, int, const T *, T *, T *, const int *, hipStream_t);            \
   template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
                                    T *, const int *, hipStream_t);                                  \
   template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \

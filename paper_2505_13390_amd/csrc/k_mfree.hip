@@ -176,6 +176,14 @@ void launch_mf_jacobi(const MfView<T> &A, const T *wdinv, const T *r, const T *z
   launch_mf_pass<T>(A, in, OpJacobi<T, InVec<T>>{wdinv, r, in, zo}, done, nullptr, s);
 }
 template <class T>
+void launch_mf_cheb(const MfView<T> &A, const T *r, const T *dinv, const T *coef,
+                    const int32_t *rowseg, int steps, int k, const T *zi, T *d, T *zo,
+                    const int *done, hipStream_t s) {
+  const InVec<T> in{zi};
+  launch_mf_pass<T>(A, in, OpCheb<T, InVec<T>>{r, dinv, d, zo, coef, rowseg, steps, k, in}, done,
+                    nullptr, s);
+}
+template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s) {
   launch_mf_pass<T>(A, InVec<T>{z}, OpResidual<T>{r, res}, done, nullptr, s);
@@ -199,7 +207,10 @@ int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, cons
   template void launch_mf_jacobi<T>(const MfView<T> &, const T *, const T *, const T *, T *,    \
                                     const int *, hipStream_t);                                  \
   template void launch_mf_residual<T>(const MfView<T> &, const T *, const T *, T *,             \
-                                      const int *, hipStream_t);
+                                      const int *, hipStream_t);                                \
+  template void launch_mf_cheb<T>(const MfView<T> &, const T *, const T *, const T *,           \
+                                  const int32_t *, int, int, const T *, T *, T *, const int *,  \
+                                  hipStream_t);
 MG_INST(double)
 MG_INST(float)
 #undef MG_INST

@@ -400,6 +400,13 @@ __global__ void k_s_pow_init(SegTab t, uint64_t salt, int level, double *__restr
 void launch_s_pow_init(const SegTab &t, uint64_t salt, int level, double *v, hipStream_t s) {
   k_s_pow_init<<<t.nblk, kBlock, 0, s>>>(t, salt, level, v);
 }
+__global__ void k_s_rowseg(SegTab t, int32_t *__restrict__ rowseg) {
+  SEG_BLOCK(t);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) rowseg[i] = seg;
+}
+void launch_s_rowseg(const SegTab &t, int32_t *rowseg, hipStream_t s) {
+  k_s_rowseg<<<t.nblk, kBlock, 0, s>>>(t, rowseg);
+}
 __global__ void k_s_wdinv(SegTab t, const double *__restrict__ omega,
                           const double *__restrict__ dinv, double *__restrict__ wdinv,
                           float *__restrict__ wdinv32) {

@@ -50,6 +50,16 @@ template <class T> void launch_residual(const CsrView<T> &A, const T *r, const T
 // with z1 = omega D^-1 r formed on the fly
 template <class T> void launch_jacobi_scaled(const CsrView<T> &A, const T *wdinv, const T *r,
                                              T *zo, const int *done, hipStream_t s);
+// Chebyshev smoothing steps (coefficient table [segment][steps][2], rowseg
+// the segment of each row or nullptr): the first step from z = 0
+// (d = c2 D^-1 r, z = d), and step k after the product A zi
+// (d = c1 d + c2 D^-1 (r - A zi), zo = zi + d; c1 unused at k = 0)
+template <class T> void launch_cheb_first(int64_t n, const T *r, const T *dinv, const T *coef,
+                                          const int32_t *rowseg, int steps, T *d, T *z,
+                                          const int *done, hipStream_t s);
+template <class T> void launch_cheb(const CsrView<T> &A, const T *r, const T *dinv,
+                                    const T *coef, const int32_t *rowseg, int steps, int k,
+                                    const T *zi, T *d, T *zo, const int *done, hipStream_t s);
 // rc[a] = sum over members i of a (ascending) of p_i res_i
 template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
                                         const int32_t *agg_mem, const T *p, const T *res, T *rc,

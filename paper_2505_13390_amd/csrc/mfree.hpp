@@ -43,6 +43,10 @@ template <class T>
 void launch_mf_jacobi(const MfView<T> &A, const T *wdinv, const T *r, const T *zi, T *zo,
                       const int *done, hipStream_t s);
 template <class T>
+void launch_mf_cheb(const MfView<T> &A, const T *r, const T *dinv, const T *coef,
+                    const int32_t *rowseg, int steps, int k, const T *zi, T *d, T *zo,
+                    const int *done, hipStream_t s);
+template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s);
 // the PCG product q = A p as its two kernels (timed one by one when

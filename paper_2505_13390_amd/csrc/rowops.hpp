@@ -35,6 +35,26 @@ struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi), wdinv = omega D^-1 per ro
     zo[i] = zi(i) + (r[i] - s) * wdinv[i];
   }
 };
+// One Chebyshev step (Saad, Alg. 12.1, M = D) after the product s = (A z_k)_i:
+// d_k = c1 d_{k-1} + c2 D^-1 (r - A z_k), z_{k+1} = z_k + d_k, with (c1, c2) of
+// step k from the coefficient table of the row's body (c1 unused at k = 0).
+template <class T, class In>
+struct OpCheb {
+  const T *r, *dinv;
+  T *d, *zo;
+  const T *coef;          // [segment][steps][2]
+  const int32_t *rowseg;  // segment of each row (nullptr: one segment)
+  int steps, k;
+  In zi;
+  __device__ void operator()(int64_t i, T s, double &) const {
+    const int64_t c = 2 * ((int64_t)(rowseg ? rowseg[i] : 0) * steps + k);
+    const T rr = (r[i] - s) * dinv[i];
+    const T dn = k == 0 ? coef[c + 1] * rr : coef[c] * d[i] + coef[c + 1] * rr;
+    d[i] = dn;
+    zo[i] = zi(i) + dn;
+  }
+};
+
 template <class T>
 struct OpResidual {  // res = r - A z
   const T *r;

@@ -62,6 +62,8 @@ void launch_s_pow_normalize(const SegTab &t, const double *w, const double *nrm2
 void launch_s_rayleigh(const SegTab &t, const double *v, const double *Av, const double *diag,
                        double *out, double *partials, hipStream_t s);
 void launch_s_pow_init(const SegTab &t, uint64_t salt, int level, double *v, hipStream_t s);
+// segment index of every row
+void launch_s_rowseg(const SegTab &t, int32_t *rowseg, hipStream_t s);
 // omega D^-1 per row (omega per segment)
 void launch_s_wdinv(const SegTab &t, const double *omega, const double *dinv, double *wdinv,
                     float *wdinv32, hipStream_t s);

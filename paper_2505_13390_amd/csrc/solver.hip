@@ -129,8 +129,9 @@ void Solver::finish_level(int l) {
   L.dinv.alloc(L.n);
   L.wdinv.alloc(L.n);
   if (mixed()) L.wdinv32.alloc(L.n);
+  if (mixed() && opt.smoother == 1) L.dinv32.alloc(L.n);
   reset_flags();
-  launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, nullptr,
+  launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, L.dinv32.p,
                       flags.p + kFBadDiag, st);
   MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN,
              "level " + std::to_string(l) + " has a non-positive diagonal entry");
@@ -140,6 +141,7 @@ void Solver::finish_level(int l) {
   L.res.alloc(L.n);
   if (mixed()) L.res32.alloc(L.n);
   power_omega(l);
+  if (opt.smoother == 1) chebyshev_table(l);
   L.d_omega.upload(L.omega.data(), L.omega.size(), st);
   launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p, mixed() ? L.wdinv32.p : nullptr,
                  st);
@@ -243,6 +245,7 @@ void Solver::power_omega(int l) {
   Level &L = *lev[l];
   const int ns = (int)L.seg.size() - 1;
   L.omega.assign(ns, 0.0);
+  L.lmax.assign(ns, 0.0);
   if (L.n == 0) return;
   SegTab t = L.tab.view();
   dscal.reserve(std::max<size_t>(16, 3 * (size_t)ns + 8));
@@ -261,9 +264,51 @@ void Solver::power_omega(int l) {
   MG_HIP(hipMemcpyAsync(h.data(), ray, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < ns; ++k) {
-    double lmax = h[2 * k] / h[2 * k + 1];
-    L.omega[k] = 2.0 / (opt.lmax_scale * lmax + opt.lambda_min);
+    L.lmax[k] = opt.lmax_scale * (h[2 * k] / h[2 * k + 1]);
+    L.omega[k] = 2.0 / (L.lmax[k] + opt.lambda_min);
   }
+}
+
+// Chebyshev smoother coefficients of every body on level l (Sec. 4.5, the
+// recurrence of Saad, Alg. 12.1, with M = D) on [lambda_min, lmax]:
+// theta = (b + a)/2, delta = (b - a)/2, sigma = theta/delta; step 0 uses
+// c2 = 1/theta; step k >= 1 uses rho_k = 1/(2 sigma - rho_{k-1}) (rho_0 =
+// 1/sigma), c1 = rho_k rho_{k-1}, c2 = 2 rho_k / delta.
+void Solver::chebyshev_table(int l) {
+  Level &L = *lev[l];
+  const int ns = (int)L.seg.size() - 1;
+  const int steps = std::max(1, std::max(opt.pre_sweeps, opt.post_sweeps));
+  std::vector<double> c((size_t)2 * steps * ns, 0.0);
+  for (int g = 0; g < ns; ++g) {
+    const double a = opt.lambda_min, b = L.lmax[g];
+    const double theta = (b + a) / 2.0, delta = (b - a) / 2.0, sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < steps; ++k) {
+      double c1 = 0.0, c2 = 1.0 / theta;
+      if (k > 0) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / delta;
+        rho = rn;
+      }
+      c[2 * ((size_t)g * steps + k)] = c1;
+      c[2 * ((size_t)g * steps + k) + 1] = c2;
+    }
+  }
+  L.cheb.upload(c.data(), c.size(), st);
+  if (mixed()) {
+    std::vector<float> f(c.begin(), c.end());
+    L.cheb32.upload(f.data(), f.size(), st);
+  }
+  if (ns > 1) {
+    L.rowseg.alloc(std::max<int64_t>(L.n, 1));
+    launch_s_rowseg(L.tab.view(), L.rowseg.p, st);
+  } else {
+    L.rowseg.release();
+  }
+  L.dir.alloc(std::max<int64_t>(L.n, 1));
+  if (mixed()) L.dir32.alloc(std::max<int64_t>(L.n, 1));
+  MG_HIP(hipStreamSynchronize(st));
 }
 
 // Aggregation of every body that coarsens further (Sec. 4.1); rows of bodies
@@ -587,7 +632,7 @@ void Solver::refresh() {
   reset_flags();
   for (int l = 0; l < nlev; ++l) {
     Level &L = *lev[l];
-    launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, nullptr,
+    launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, L.dinv32.p,
                         flags.p + kFBadDiag, st);
     launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p,
                    mixed() ? L.wdinv32.p : nullptr, st);
@@ -613,6 +658,9 @@ template <> struct Buf<double> {
   static DevBuf<double> &res(Level &L) { return L.res; }
   static CsrView<double> A(const Level &L) { return L.view(); }
   static const double *wdinv(const Level &L) { return L.wdinv.p; }
+  static const double *dinv(const Level &L) { return L.dinv.p; }
+  static const double *cheb(const Level &L) { return L.cheb.p; }
+  static double *dir(Level &L) { return L.dir.p; }
   static const double *p(const Level &L) { return L.p.p; }
 };
 template <> struct Buf<float> {
@@ -622,6 +670,9 @@ template <> struct Buf<float> {
   static DevBuf<float> &res(Level &L) { return L.res32; }
   static CsrView<float> A(const Level &L) { return L.view32(); }
   static const float *wdinv(const Level &L) { return L.wdinv32.p; }
+  static const float *dinv(const Level &L) { return L.dinv32.p; }
+  static const float *cheb(const Level &L) { return L.cheb32.p; }
+  static float *dir(Level &L) { return L.dir32.p; }
   static const float *p(const Level &L) { return L.p32.p; }
 };
 
@@ -652,7 +703,9 @@ void Solver::vcycle(int l, const T *r, T *z) {
   // z1 = omega D^-1 r on the fly. A matrix-free level keeps the elementwise
   // first sweep: its gather would fetch two vectors per incidence instead of
   // one, which costs more than the separate kernel.
-  const bool fuse = (M == nullptr);
+  const bool fuse = (M == nullptr) && opt.smoother == 0;
+  const bool cheb = opt.smoother == 1;
+  const int steps = std::max(1, std::max(pre, post));
   // The iterate ping-pongs between z and the level's scratch vector; the
   // first target is chosen so that the last write lands in z.
   const int pre_writes = pre == 0 ? 1 : (fuse && pre >= 2) ? pre - 1 : pre;
@@ -660,14 +713,26 @@ void Solver::vcycle(int l, const T *r, T *z) {
   T *bufs[2] = {z, Buf<T>::t(L).p};
   int w = (writes % 2) ? 0 : 1;
   auto next = [&]() { return bufs[(w++) % 2]; };
-  auto sweep = [&](const T *zi, T *zo) {
-    if (M) launch_mf_jacobi<T>(*M, wd, r, zi, zo, done, st);
-    else launch_jacobi<T>(A, wd, r, zi, zo, done, st);
+  // sweep k of a smoothing pass: a Jacobi sweep or Chebyshev step k
+  auto sweep = [&](int k, const T *zi, T *zo) {
+    if (cheb) {
+      const T *dv = Buf<T>::dinv(L), *cf = Buf<T>::cheb(L);
+      T *d = Buf<T>::dir(L);
+      if (M) launch_mf_cheb<T>(*M, r, dv, cf, L.rowseg.p, steps, k, zi, d, zo, done, st);
+      else launch_cheb<T>(A, r, dv, cf, L.rowseg.p, steps, k, zi, d, zo, done, st);
+    } else if (M) {
+      launch_mf_jacobi<T>(*M, wd, r, zi, zo, done, st);
+    } else {
+      launch_jacobi<T>(A, wd, r, zi, zo, done, st);
+    }
   };
   T *cur = next();
   int k0 = 1;
   if (pre == 0) {
     launch_zero_t<T>(L.n, cur, done, st);
+  } else if (cheb) {
+    launch_cheb_first<T>(L.n, r, Buf<T>::dinv(L), Buf<T>::cheb(L), L.rowseg.p, steps,
+                         Buf<T>::dir(L), cur, done, st);
   } else if (fuse && pre >= 2) {
     launch_jacobi_scaled<T>(A, wd, r, cur, done, st);
     k0 = 2;
@@ -676,7 +741,7 @@ void Solver::vcycle(int l, const T *r, T *z) {
   }
   for (int k = k0; k < pre; ++k) {
     T *o = next();
-    sweep(cur, o);
+    sweep(k, cur, o);
     cur = o;
   }
   if (coarse) {
@@ -692,7 +757,7 @@ void Solver::vcycle(int l, const T *r, T *z) {
   }
   for (int k = 0; k < post; ++k) {
     T *o = next();
-    sweep(cur, o);
+    sweep(k, cur, o);
     cur = o;
   }
   if (cur != z) launch_copy_t<T>(L.n, cur, z, done, st);   // not reached: w makes cur == z

@@ -29,11 +29,17 @@ struct Level {
   DevBuf<float> val32;
   DevBuf<int64_t> diagpos;
   DevBuf<double> diag, dinv, wdinv;   // wdinv = omega(body) / a_ii
-  DevBuf<float> wdinv32;
+  DevBuf<float> wdinv32, dinv32;
+  // Chebyshev smoother: coefficient table [segment][step][2], row -> segment
+  // (several segments only), search direction
+  DevBuf<double> cheb, dir;
+  DevBuf<float> cheb32, dir32;
+  DevBuf<int32_t> rowseg;
   // bodies present on this level
   std::vector<int64_t> seg;           // row offsets, one segment per body
   std::vector<int32_t> body;          // body id of each segment
   std::vector<double> omega;          // Jacobi weight of each segment
+  std::vector<double> lmax;           // lmax_scale * lambda_max estimate of each segment
   std::vector<char> terminal;         // the body has no coarser level
   SegTable tab;
   DevBuf<double> d_omega;
@@ -169,6 +175,7 @@ class Solver {
   void galerkin_numeric(int l);
   void power_omega(int l);
   void tune_lanes(int l);
+  void chebyshev_table(int l);
   void plan_dense();
   void factor_dense();
   void iterate_once(int k);

@@ -47,6 +47,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.use_graph == 1 and o.check_every == 8 and o.profile_spmv == 0
     assert o.spmv_tile == 0 and o.spmv_lanes == 0
     assert o.matrix_free == 1
+    assert o.smoother == 0
 
 
 def test_null_arguments_rejected_without_device_work():
