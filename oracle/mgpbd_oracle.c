@@ -35,7 +35,11 @@
  *    Optionally the Chebyshev smoother of the same subsection: s steps of
  *    Chebyshev acceleration of Jacobi on the interval [lambda_min, lambda_max]
  *    (the recurrence of Saad, Iterative Methods for Sparse Linear Systems,
- *    2nd ed., Alg. 12.1, with M = D), coefficients fixed at setup.
+ *    2nd ed., Alg. 12.1, with M = D), coefficients fixed at setup; or the
+ *    parallel (multicolour) Gauss-Seidel smoother: colours of every level from
+ *    a greedy colouring in descending priority, forward colour order before
+ *    the coarse correction and reversed order after it (the adjoint, so the
+ *    V-cycle stays symmetric).
  *
  * Readings where the paper is silent (each listed in the design notes):
  *  - one near-kernel candidate per aggregate (K = 1): P column = candidate
@@ -81,7 +85,7 @@ typedef struct orc_opts {
   double eps_b;        /* stop the frame loop when |b| < eps_b (0 = never) */
   int flexible;        /* 0 = Fletcher-Reeves beta, 1 = Polak-Ribiere beta */
   double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 */
-  int smoother;        /* 0 = omega-Jacobi, 1 = Chebyshev (Sec. 4.5): 0 */
+  int smoother;        /* 0 = omega-Jacobi, 1 = Chebyshev, 2 = multicolour GS (Sec. 4.5): 0 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -474,6 +478,10 @@ typedef struct {
   double *B;          /* near-kernel candidate on this level */
   int32_t *color;     /* level 0: multicolour GS order */
   int n_colors;
+  /* Gauss-Seidel smoother: rows grouped by colour */
+  int sm_colors;
+  int64_t *sm_ptr;
+  int32_t *sm_rows;
 } level_t;
 
 typedef struct {
@@ -490,7 +498,7 @@ typedef struct {
 static void level_free(level_t *lv) {
   csr_free(&lv->A);
   free(lv->diag); free(lv->agg); free(lv->agg_ptr); free(lv->agg_mem);
-  free(lv->p); free(lv->B); free(lv->color);
+  free(lv->p); free(lv->B); free(lv->color); free(lv->sm_ptr); free(lv->sm_rows);
   memset(lv, 0, sizeof *lv);
 }
 
@@ -808,6 +816,24 @@ static int finish_level(hier_t *h, int l) {
   lv->lmax = nl ? h->o.lmax_scale * power_lmax(&lv->A, lv->diag, h->o.power_iters, h->o.seed, l)
                : 0.0;
   lv->omega = nl ? 2.0 / (lv->lmax + h->o.lambda_min) : 0.0;
+  if (h->o.smoother == 2) {
+    /* rows of each colour in ascending order (greedy colouring in
+       descending priority, the order the near-kernel sweeps use) */
+    uint64_t *cp = malloc(sizeof(uint64_t) * (nl ? nl : 1));
+    int32_t *color = malloc(sizeof(int32_t) * (nl ? nl : 1));
+    if (!cp || !color) { free(cp); free(color); return ORC_E_NOMEM; }
+    for (int64_t i = 0; i < nl; ++i) cp[i] = prio_key(h->o.seed, 4, l, i);
+    lv->sm_colors = orc_color(nl, lv->A.rowptr, lv->A.col, cp, color);
+    lv->sm_ptr = calloc(lv->sm_colors + 1, sizeof(int64_t));
+    lv->sm_rows = malloc(sizeof(int32_t) * (nl ? nl : 1));
+    if (!lv->sm_ptr || !lv->sm_rows) { free(cp); free(color); return ORC_E_NOMEM; }
+    for (int64_t i = 0; i < nl; ++i) lv->sm_ptr[color[i] + 1]++;
+    for (int c = 0; c < lv->sm_colors; ++c) lv->sm_ptr[c + 1] += lv->sm_ptr[c];
+    int64_t *cur = malloc(sizeof(int64_t) * (lv->sm_colors ? lv->sm_colors : 1));
+    memcpy(cur, lv->sm_ptr, sizeof(int64_t) * lv->sm_colors);
+    for (int64_t i = 0; i < nl; ++i) lv->sm_rows[cur[color[i]]++] = (int32_t)i;
+    free(cur); free(cp); free(color);
+  }
   return ORC_OK;
 }
 
@@ -942,6 +968,25 @@ int orc_hier_refresh(hier_t *h, const double *val0) {
   return ORC_OK;
 }
 
+/* Multicolour Gauss-Seidel sweeps for A z = r on level l: within a colour the
+   rows are independent, z_i <- (r_i - sum_{j != i, ascending} a_ij z_j) / a_ii;
+   colours in ascending order (forward) or descending order (backward). */
+static void gs_smooth(hier_t *h, int l, const double *r, double *z, int sweeps, int backward) {
+  level_t *lv = &h->lev[l];
+  const csr *a = &lv->A;
+  for (int s = 0; s < sweeps; ++s)
+    for (int q = 0; q < lv->sm_colors; ++q) {
+      int c = backward ? lv->sm_colors - 1 - q : q;
+      for (int64_t t = lv->sm_ptr[c]; t < lv->sm_ptr[c + 1]; ++t) {
+        int32_t i = lv->sm_rows[t];
+        double acc = 0.0;
+        for (int64_t e = a->rowptr[i]; e < a->rowptr[i + 1]; ++e)
+          if (a->col[e] != i) acc = acc + a->val[e] * z[a->col[e]];
+        z[i] = (r[i] - acc) / lv->diag[i];
+      }
+    }
+}
+
 /* Chebyshev smoothing on level l: `steps` steps of Chebyshev acceleration of
    Jacobi for A z = r on the eigenvalue interval [a, b] = [lambda_min, lmax]
    of D^-1 A: theta = (b + a)/2, delta = (b - a)/2, sigma = theta/delta,
@@ -989,9 +1034,12 @@ static void vcycle(hier_t *h, int l, const double *r, double *z) {
   if (l == h->L - 1 && h->last_dense) { chol_solve(h, r, z); return; }
   double om = lv->omega;
   double *t = h->tmp[l];
-  const int cheb = h->o.smoother == 1;
+  const int cheb = h->o.smoother == 1, gs = h->o.smoother == 2;
   if (h->o.pre_sweeps == 0) {
     for (int64_t i = 0; i < n; ++i) z[i] = 0.0;
+  } else if (gs) {
+    for (int64_t i = 0; i < n; ++i) z[i] = 0.0;
+    gs_smooth(h, l, r, z, h->o.pre_sweeps, 0);
   } else if (cheb) {
     cheb_smooth(h, l, r, z, h->o.pre_sweeps, 1);
   } else {
@@ -1019,7 +1067,9 @@ static void vcycle(hier_t *h, int l, const double *r, double *z) {
     for (int64_t i = 0; i < n; ++i)
       if (lv->agg[i] >= 0) z[i] = z[i] + lv->p[i] * zc[lv->agg[i]];
   }
-  if (cheb) {
+  if (gs) {
+    gs_smooth(h, l, r, z, h->o.post_sweeps, 1);
+  } else if (cheb) {
     cheb_smooth(h, l, r, z, h->o.post_sweeps, 0);
   } else {
     for (int s = 0; s < h->o.post_sweeps; ++s) {

@@ -676,8 +676,8 @@ def test_zero_sweeps_leave_only_the_coarse_correction():
     assert not np.any(h.vcycle(rng.standard_normal(8)))
 
 
-@pytest.mark.parametrize("smoother", [0, 1])
-def test_vcycle_symmetric_positive_both_smoothers(smoother):
+@pytest.mark.parametrize("smoother", [0, 1, 2])
+def test_vcycle_symmetric_positive_all_smoothers(smoother):
     w, s, rp, col, val, b, h = small_hier(smoother=smoother)
     assert h.levels >= 2
     rng = np.random.default_rng(5)
@@ -686,3 +686,51 @@ def test_vcycle_symmetric_positive_both_smoothers(smoother):
         a1, a2 = z @ h.vcycle(y), y @ h.vcycle(z)
         assert abs(a1 - a2) <= 1e-12 * (abs(a1) + abs(a2))
         assert y @ h.vcycle(y) > 0
+
+
+def smoother_colors(A, level=0, seed=20250513):
+    """The colouring the Gauss-Seidel smoother uses on a level: greedy in
+    descending priority key (stream 4, level-salted), via the oracle's own
+    colouring routine."""
+    As = sp.csr_matrix(A)
+    As.sort_indices()
+    n = As.shape[0]
+    keys = np.array([(O.mix64(seed, 4, (level << 40) + i) & 0xFFFFFFFF00000000) | i
+                     for i in range(n)], dtype=np.uint64)
+    c, nc = O.color(As.indptr.astype(np.int64), As.indices, keys)
+    return c, nc
+
+
+def test_gauss_seidel_smoother_is_the_splitting_iteration():
+    """Sec. 4.5, parallel Gauss-Seidel: a forward sweep over the colours is the
+    Gauss-Seidel splitting x <- (D + L)^-1 (r - U x) of A in colour order (rows
+    of one colour are independent), the backward sweep uses (D + U)^-1; one
+    V-cycle of a one-level hierarchy is s forward sweeps from zero followed by
+    s backward sweeps. Dense triangular solves (numpy) against the oracle."""
+    rng = np.random.default_rng(25)
+    for trial in range(3):
+        w = W.perturbed(W.tiny_beam(3, 2, 1, volumes=True, alpha_edge=1e-6, alpha_vol=1e-7,
+                                    seed=40 + trial), 0.01, seed=trial)
+        sim = O.Sim(w)
+        val, _ = sim.assemble(w.x0)
+        rp, col = sim.pattern()
+        A = dense(rp, col, val)
+        n = A.shape[0]
+        c, nc = smoother_colors(A)
+        order = np.lexsort((np.arange(n), c))
+        Ap = A[np.ix_(order, order)]
+        Dl = np.tril(Ap)            # D + L in colour order
+        Du = np.triu(Ap)            # D + U
+        for s_ in (1, 2):
+            h, o = one_level_smoother_hier(A, smoother=2, pre_sweeps=s_, post_sweeps=s_)
+            r = rng.standard_normal(n)
+            rp_ = r[order]
+            x = np.zeros(n)
+            for _ in range(s_):
+                x = np.linalg.solve(Dl, rp_ - (Ap - Dl) @ x)
+            for _ in range(s_):
+                x = np.linalg.solve(Du, rp_ - (Ap - Du) @ x)
+            ref = np.empty(n)
+            ref[order] = x
+            z = h.vcycle(r)
+            assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max(), (trial, s_)
