@@ -110,7 +110,7 @@ def bench_batch(args, B, W):
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   matrix_free=1 if args.fine == "mf" else 0,
-                                  smoother=1 if args.smoother == "chebyshev" else 0)
+                                  smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
     rows = [w.n_rows for w in ws]
@@ -173,8 +173,9 @@ def main():
     ap.add_argument("--max-pcg", type=int, default=None)
     ap.add_argument("--fine", default="mf", choices=["mf", "csr"],
                     help="fine-level products: matrix-free (default) or assembled CSR")
-    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev"],
-                    help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default) or Chebyshev")
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev", "gs"],
+                    help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default), Chebyshev or "
+                         "multicolour Gauss-Seidel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -205,7 +206,7 @@ def main():
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   profile_spmv=0 if args.no_profile else 1,
                                   matrix_free=1 if args.fine == "mf" else 0,
-                                  smoother=1 if args.smoother == "chebyshev" else 0)
+                                  smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
     t0 = time.perf_counter()

@@ -91,7 +91,10 @@ typedef struct {
   int32_t smoother;     /* V-cycle smoother (Sec. 4.5): 0 = omega-Jacobi, 1 = Chebyshev
                            (pre_sweeps / post_sweeps steps of Chebyshev acceleration of
                            Jacobi on [lambda_min, lmax_scale * lambda_max] of D^-1 A,
-                           coefficients fixed at setup): 0 */
+                           coefficients fixed at setup), 2 = multicolour Gauss-Seidel
+                           (greedy colouring of every level at setup; forward colour
+                           order before the coarse correction, reversed after; the
+                           sweeps read the assembled values): 0 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.

@@ -109,8 +109,8 @@ void check_options(const mgpbd_options &o) {
              MGPBD_E_INVALID_ARG, "spmv_lanes must be 0, 4, 8, 16, 32 or 64");
   MG_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, MGPBD_E_INVALID_ARG,
              "matrix_free must be 0 or 1");
-  MG_REQUIRE(o.smoother == 0 || o.smoother == 1, MGPBD_E_INVALID_ARG,
-             "smoother must be 0 (omega-Jacobi) or 1 (Chebyshev)");
+  MG_REQUIRE(o.smoother >= 0 && o.smoother <= 2, MGPBD_E_INVALID_ARG,
+             "smoother must be 0 (omega-Jacobi), 1 (Chebyshev) or 2 (Gauss-Seidel)");
 }
 
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {

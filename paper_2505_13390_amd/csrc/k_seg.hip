@@ -462,13 +462,15 @@ void launch_s_mis_init(const SegTab &t, const uint8_t *conn, uint64_t salt, int 
                        uint64_t *key, hipStream_t s) {
   k_s_mis_init<<<t.nblk, kBlock, 0, s>>>(t, conn, salt, level, key);
 }
-__global__ void k_s_color_keys(SegTab t, uint64_t salt, uint64_t *__restrict__ key) {
+__global__ void k_s_color_keys(SegTab t, uint64_t salt, int level, uint64_t *__restrict__ key) {
   SEG_BLOCK(t);
   const int64_t base = t.segoff[seg];
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) key[i] = prio_key(salt, 0, i - base);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+    key[i] = prio_key(salt, level, i - base);
 }
-void launch_s_color_keys(const SegTab &t, uint64_t salt, uint64_t *key, hipStream_t s) {
-  k_s_color_keys<<<t.nblk, kBlock, 0, s>>>(t, salt, key);
+void launch_s_color_keys(const SegTab &t, uint64_t salt, int level, uint64_t *key,
+                         hipStream_t s) {
+  k_s_color_keys<<<t.nblk, kBlock, 0, s>>>(t, salt, level, key);
 }
 
 // one wavefront per row over all jobs; rowstart[j] = first global wave row of

@@ -467,6 +467,51 @@ void launch_gs_color(int64_t cnt, const int32_t *rows, const CsrView<double> &A,
   if (cnt) k_gs_color<<<blocks_for(cnt, kBlock), kBlock, 0, s>>>(cnt, rows, A.rowptr, A.col, A.val, diag, x);
 }
 
+// one colour of a Gauss-Seidel sweep for A x = r (smoother):
+// x_i <- (r_i - sum_{j != i} a_ij x_j) * dinv_i, G lanes per row
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_gs_rhs(int64_t cnt, const int32_t *__restrict__ rows,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const T *__restrict__ dinv,
+                                                   const T *__restrict__ r, T *x,
+                                                   const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(cnt, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    const int64_t k = base + grp;
+    const bool ok = k < hi;
+    const int32_t i = ok ? rows[k] : 0;
+    T s = 0;
+    if (ok)
+      for (int64_t e = rp[i] + sub; e < rp[i + 1]; e += G) {
+        const int32_t j = col[e];
+        if (j != i) s += val[e] * x[j];
+      }
+    s = group_sum<G, T>(s);
+    if (ok && sub == 0) x[i] = (r[i] - s) * dinv[i];
+  }
+}
+template <class T>
+void launch_gs_rhs(int64_t cnt, const int32_t *rows, const CsrView<T> &A, const T *dinv,
+                   const T *r, T *x, const int *done, hipStream_t s) {
+  if (!cnt) return;
+  const int grid = grid_for(cnt * A.lanes, kBlock);
+#define L_(G) k_gs_rhs<G, T><<<grid, kBlock, 0, s>>>(cnt, rows, A.rowptr, A.col, A.val, dinv, r, x, done)
+  MG_DISPATCH_G(A.lanes, L_);
+#undef L_
+}
+template void launch_gs_rhs<double>(int64_t, const int32_t *, const CsrView<double> &,
+                                    const double *, const double *, double *, const int *,
+                                    hipStream_t);
+template void launch_gs_rhs<float>(int64_t, const int32_t *, const CsrView<float> &,
+                                   const float *, const float *, float *, const int *,
+                                   hipStream_t);
+
 __global__ void k_normalize(int64_t na, const int64_t *__restrict__ ap,
                             const int32_t *__restrict__ mem, const double *__restrict__ B,
                             double *__restrict__ p, float *__restrict__ p32,

@@ -75,7 +75,8 @@ void launch_s_candidate_init(const SegTab &t, uint64_t salt, const unsigned long
 // aggregation / colouring keys from body-local row indices
 void launch_s_mis_init(const SegTab &t, const uint8_t *conn, uint64_t salt, int level,
                        uint64_t *key, hipStream_t s);
-void launch_s_color_keys(const SegTab &t, uint64_t salt, uint64_t *key, hipStream_t s);
+void launch_s_color_keys(const SegTab &t, uint64_t salt, int level, uint64_t *key,
+                         hipStream_t s);
 
 // ---- dense coarsest blocks of several bodies ----
 struct DenseJob {        // one body's last level

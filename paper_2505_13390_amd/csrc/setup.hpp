@@ -40,6 +40,10 @@ void launch_scatter_colors(int64_t n, const int32_t *color, const int64_t *off, 
 // one colour of a Gauss-Seidel sweep on A x = 0
 void launch_gs_color(int64_t cnt, const int32_t *rows, const CsrView<double> &A,
                      const double *diag, double *x, hipStream_t s);
+// one colour of a Gauss-Seidel smoothing sweep for A x = r
+template <class T>
+void launch_gs_rhs(int64_t cnt, const int32_t *rows, const CsrView<T> &A, const T *dinv,
+                   const T *r, T *x, const int *done, hipStream_t s);
 // one-column QR per aggregate: p = B / |B|_aggregate, Bn = |B|_aggregate
 void launch_normalize(int64_t na, const int64_t *ap, const int32_t *mem, const double *B,
                       double *p, float *p32, double *Bn, hipStream_t s);

@@ -129,7 +129,7 @@ void Solver::finish_level(int l) {
   L.dinv.alloc(L.n);
   L.wdinv.alloc(L.n);
   if (mixed()) L.wdinv32.alloc(L.n);
-  if (mixed() && opt.smoother == 1) L.dinv32.alloc(L.n);
+  if (mixed() && opt.smoother != 0) L.dinv32.alloc(L.n);
   reset_flags();
   launch_extract_diag(L.n, L.diagpos.p, L.val.p, L.diag.p, L.dinv.p, L.dinv32.p,
                       flags.p + kFBadDiag, st);
@@ -142,6 +142,7 @@ void Solver::finish_level(int l) {
   if (mixed()) L.res32.alloc(L.n);
   power_omega(l);
   if (opt.smoother == 1) chebyshev_table(l);
+  if (opt.smoother == 2) colour_level(l);
   L.d_omega.upload(L.omega.data(), L.omega.size(), st);
   launch_s_wdinv(L.tab.view(), L.d_omega.p, L.dinv.p, L.wdinv.p, mixed() ? L.wdinv32.p : nullptr,
                  st);
@@ -359,28 +360,18 @@ std::vector<int64_t> Solver::aggregate(int l) {
   return first;
 }
 
-// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|)
-// of its body, then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
-void Solver::candidate0() {
-  Level &L = *lev[0];
+// Greedy colouring of level l in descending priority (Jones-Plassmann by
+// counters; keys from body-local indices, so each body is coloured as if it
+// were alone) and the rows of each colour: the order of the near-kernel
+// sweeps (level 0) and of the Gauss-Seidel smoother (every level).
+void Solver::colour_level(int l) {
+  Level &L = *lev[l];
   const int64_t n = L.n;
-  const int ns = (int)L.seg.size() - 1;
-  L.B.alloc(n);
-  if (opt.b_mode == 1) {
-    launch_fill(n, 1.0, L.B.p, st);
-    return;
-  }
   CsrView<double> A = L.view();
   SegTab t = L.tab.view();
-  amax.reserve(ns);
-  MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * ns, st));
-  launch_s_absmax(t, L.rowptr.p, L.val.p, amax.p, st);
-  launch_s_candidate_init(t, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
-  // greedy colouring (Jones-Plassmann rounds); keys from body-local indices
-  // colour each body as if it were alone
   key.reserve(n);
   L.color.alloc(n);
-  launch_s_color_keys(t, stream_salt(opt.seed, kStreamColorPrio), key.p, st);
+  launch_s_color_keys(t, stream_salt(opt.seed, kStreamColorPrio), l, key.p, st);
   launch_fill_i32(n, -1, L.color.p, st);
   {
     itmp.reserve(n);             // higher-priority neighbour counts
@@ -420,6 +411,27 @@ void Solver::candidate0() {
   MG_HIP(hipMemsetAsync(itmp.p, 0, 256 * sizeof(int32_t), st));
   L.color_rows.alloc(n);
   launch_scatter_colors(n, L.color.p, ltmp2.p, itmp.p, L.color_rows.p, st);
+  MG_HIP(hipStreamSynchronize(st));
+}
+
+// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|)
+// of its body, then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
+void Solver::candidate0() {
+  Level &L = *lev[0];
+  const int64_t n = L.n;
+  const int ns = (int)L.seg.size() - 1;
+  L.B.alloc(n);
+  if (opt.b_mode == 1) {
+    launch_fill(n, 1.0, L.B.p, st);
+    return;
+  }
+  CsrView<double> A = L.view();
+  SegTab t = L.tab.view();
+  amax.reserve(ns);
+  MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * ns, st));
+  launch_s_absmax(t, L.rowptr.p, L.val.p, amax.p, st);
+  launch_s_candidate_init(t, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
+  if (opt.smoother != 2) colour_level(0);   // (the Gauss-Seidel smoother coloured it already)
   for (int s = 0; s < opt.gs_sweeps; ++s)
     for (int c = 0; c < L.n_colors; ++c)
       launch_gs_color(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
@@ -685,6 +697,43 @@ const MfView<float> *Solver::level_mf<float>(int l) const {
   return (l == 0 && mf32.ok()) ? &mf32 : nullptr;
 }
 
+// V-cycle on level l with the multicolour Gauss-Seidel smoother (Sec. 4.5):
+// from z = 0, pre_sweeps forward sweeps over the colours, coarse
+// correction, post_sweeps sweeps in reversed colour order. The sweeps read
+// the assembled values on every level (also where the products are
+// matrix-free): each colour needs the latest values of its neighbours.
+template <class T>
+void Solver::gs_vcycle(int l, const T *r, T *z) {
+  Level &L = *lev[l];
+  const int *done = done_ptr();
+  const CsrView<T> A = Buf<T>::A(L);
+  const T *dv = Buf<T>::dinv(L);
+  auto sweep = [&](bool backward) {
+    for (int q = 0; q < L.n_colors; ++q) {
+      const int c = backward ? L.n_colors - 1 - q : q;
+      launch_gs_rhs<T>(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
+                       dv, r, z, done, st);
+    }
+  };
+  launch_zero_t<T>(L.n, z, done, st);
+  for (int k = 0; k < opt.pre_sweeps; ++k) sweep(false);
+  if (l + 1 < nlev) {
+    Level &C = *lev[l + 1];
+    T *rc = Buf<T>::r(C).p, *ec = Buf<T>::z(C).p;
+    const T *pl = Buf<T>::p(L);
+    T *res = Buf<T>::res(L).p;
+    if (const MfView<T> *M = level_mf<T>(l)) launch_mf_residual<T>(*M, r, z, res, done, st);
+    else launch_residual<T>(A, r, z, res, done, st);
+    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, pl, res, rc, done, st);
+    vcycle<T>(l + 1, rc, ec);
+    launch_prolong<T>(L.n, L.agg.p, pl, ec, z, done, st);
+  }
+  for (int k = 0; k < opt.post_sweeps; ++k) sweep(true);
+  if (!L.jobs.empty())
+    launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
+                                Ainv.p, r, z, done, st);
+}
+
 template <class T>
 void Solver::vcycle(int l, const T *r, T *z) {
   Level &L = *lev[l];
@@ -726,6 +775,10 @@ void Solver::vcycle(int l, const T *r, T *z) {
       launch_jacobi<T>(A, wd, r, zi, zo, done, st);
     }
   };
+  if (opt.smoother == 2) {   // Gauss-Seidel: in place on z
+    gs_vcycle<T>(l, r, z);
+    return;
+  }
   T *cur = next();
   int k0 = 1;
   if (pre == 0) {

@@ -170,6 +170,7 @@ class Solver {
   void finish_level(int l);
   std::vector<int64_t> aggregate(int l);
   void candidate0();
+  void colour_level(int l);
   void build_members(int l);
   void galerkin_symbolic(int l);
   void galerkin_numeric(int l);
@@ -180,6 +181,7 @@ class Solver {
   void factor_dense();
   void iterate_once(int k);
   template <class T> void vcycle(int l, const T *r, T *z);
+  template <class T> void gs_vcycle(int l, const T *r, T *z);
   template <class T> const MfView<T> *level_mf(int l) const;
 };
 

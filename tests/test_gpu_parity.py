@@ -305,31 +305,34 @@ def test_create_rejects_bad_input():
                        w.gravity, go)
 
 
-@pytest.mark.parametrize("mf", [1, 0])
-def test_chebyshev_smoother_against_oracle(mf):
-    """Sec. 4.5's Chebyshev smoother (2 steps before and after) on both fine
-    operators: positions within 1e-9 of the oracle running the same smoother."""
+@pytest.mark.parametrize("smoother,mf", [(1, 1), (1, 0), (2, 1), (2, 0)])
+def test_other_smoothers_against_oracle(smoother, mf):
+    """Sec. 4.5's Chebyshev (1) and multicolour Gauss-Seidel (2) smoothers, 2
+    sweeps before and after, with both fine operators: positions within 1e-9
+    of the oracle running the same smoother."""
     w = W.beam_c0()
-    sim, body, pos, vel, ores, gres = run_both(w, 8, smoother=1, matrix_free=mf)
+    sim, body, pos, vel, ores, gres = run_both(w, 8, smoother=smoother, matrix_free=mf)
     err = rel_pos_err(body.positions(), pos)
-    log("Chebyshev (matrix_free=%d): oracle iters %s gpu %s err %.3e"
-        % (mf, ores[0]["pcg_iters"].tolist(), gres[0]["pcg_iters"].tolist(), err))
+    log("smoother %d (matrix_free=%d): oracle iters %s gpu %s err %.3e"
+        % (smoother, mf, ores[0]["pcg_iters"].tolist(), gres[0]["pcg_iters"].tolist(), err))
     assert (gres[0]["pcg_ratio"] <= 1e-6).all()
     for a, b in zip(ores[0]["pcg_iters"], gres[0]["pcg_iters"]):
         assert iters_close(a, b)
     assert err <= 1e-9
 
 
-def test_chebyshev_smoother_mixed_and_batched():
-    """FP32 V-cycle with the Chebyshev smoother, and a batch of bodies with
-    their own Chebyshev coefficients, against the FP64 oracle."""
+@pytest.mark.parametrize("smoother", [1, 2])
+def test_other_smoothers_mixed_and_batched(smoother):
+    """FP32 V-cycle with the Chebyshev or Gauss-Seidel smoother, on a batch of
+    bodies with their own coefficients and colourings, against the FP64
+    oracle."""
     ws = [W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8, seed=31),
           W.tiny_beam(3, 1, 1, seed=32),
           W.perturbed(W.tiny_beam(20, 3, 3, volumes=True, alpha_edge=1e-7, alpha_vol=1e-8,
                                   seed=33), 1e-3)]
-    oo, _ = opts(smoother=1, coarse_max=60)
+    oo, _ = opts(smoother=smoother, coarse_max=60)
     for prec, bound in ((B.PREC_FP64, 1e-9), (B.PREC_MIXED, 1e-7)):
-        _, go = opts(smoother=1, coarse_max=60, precision=prec)
+        _, go = opts(smoother=smoother, coarse_max=60, precision=prec)
         batch = B.Batch(ws, go)
         res = batch.step(5)
         for k, w in enumerate(ws):
@@ -337,8 +340,8 @@ def test_chebyshev_smoother_mixed_and_batched():
             pos, vel = O.positions(w)
             sim.step(pos, vel, 5)
             err = rel_pos_err(batch.bodies[k].positions(), pos)
-            log("Chebyshev batch precision %d body %d: iters %s err %.3e"
-                % (prec, k, res[k]["pcg_iters"].tolist(), err))
+            log("smoother %d batch precision %d body %d: iters %s err %.3e"
+                % (smoother, prec, k, res[k]["pcg_iters"].tolist(), err))
             assert (res[k]["pcg_ratio"] <= 1e-6).all()
             assert err <= bound
         batch.close()
