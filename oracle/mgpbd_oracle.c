@@ -40,6 +40,9 @@
  *    a greedy colouring in descending priority, forward colour order before
  *    the coarse correction and reversed order after it (the adjoint, so the
  *    V-cycle stays symmetric).
+ *  - Sec. 6 (As-Rigid-As-Possible constraints): a tet row with
+ *    C = |F - R|_F^2, F the deformation gradient and R its nearest rotation
+ *    (arap_eval, with the readings listed there).
  *
  * Readings where the paper is silent (each listed in the design notes):
  *  - one near-kernel candidate per aggregate (K = 1): P column = candidate
@@ -180,12 +183,14 @@ static double dot(int64_t n, const double *x, const double *y) {
 /* The simulated body: vertices, constraint rows, fixed pattern of A   */
 /* ------------------------------------------------------------------ */
 typedef struct {
-  int64_t n_verts, n_tets, n_edges, n_vols, m;
+  int64_t n_verts, n_tets, n_edges, n_vols, n_arap, m;
   double *rest, *w;      /* rest[N][3], inverse masses */
   int32_t *tets;         /* [T][4] */
   int32_t *rv;           /* vertices of each row: [m][4], -1 padding */
-  int *rk;               /* arity of each row: 2 (edge) or 4 (volume) */
-  double *rest_c;        /* L0 or V0 per row */
+  int *rk;               /* arity of each row: 2 (edge) or 4 (volume, ARAP) */
+  int *arap;             /* 1 for an ARAP row, else 0 */
+  double *dm_inv;        /* [m][9] inverse rest shape matrix of ARAP rows, row-major */
+  double *rest_c;        /* L0 or V0 per row (0 for ARAP rows) */
   double *alpha_t;       /* alpha / dt^2 per row */
   double dt, g[3];
   orc_opts o;
@@ -200,13 +205,201 @@ typedef struct {
   void *hier;
 } orc_sim;
 
+/* ------------------------------------------------------------------ */
+/* ARAP constraint (Sec. 6, As-Rigid-As-Possible Constraints)          */
+/* ------------------------------------------------------------------ */
+/* Per tet (x0, x1, x2, x3): Ds = [x1 - x0, x2 - x0, x3 - x0] (columns),
+   Dm the same matrix at rest, F = Ds Dm^-1 the deformation gradient and
+   C = |F - R|_F^2 with R the rotation of F.
+   Readings (the paper defers the details to Kim and Eberle's 2020 course
+   notes on deformables):
+    - R is the rotation (det R = +1) nearest to F in the Frobenius norm, i.e.
+      U V^T from the signed SVD F = U S V^T with U, V rotations and the sign of
+      det F carried by the smallest singular value; an inverted tet therefore
+      has C > 0 and is pushed back. When it is not unique (rank(F) <= 1),
+      R = I.
+    - C(F) = min over rotations Q of |F - Q|^2, so by the envelope theorem
+      dC/dF = 2 (F - R) wherever R is unique. With F = Ds Dm^-1,
+      dC/dDs = 2 (F - R) Dm^-T, whose column i - 1 is dC/dx_i (i = 1, 2, 3),
+      and dC/dx_0 = -(dC/dx_1 + dC/dx_2 + dC/dx_3).
+    - The row's target is C = 0 (rest_c = 0); its compliance alpha is an
+      input (the paper takes alpha = 1 / (mu V_rest)).
+   Matrices are row-major 3x3: M[3 * i + j]. */
+
+static void mat3_mul(const double *a, const double *b, double *o) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      o[3 * i + j] = (a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j]) + a[3 * i + 2] * b[6 + j];
+}
+
+static void mat3_transpose(const double *a, double *o) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) o[3 * j + i] = a[3 * i + j];
+}
+
+/* Inverse by Gauss-Jordan elimination with partial pivoting; returns 0 if
+   the matrix is singular. */
+static int mat3_inverse(const double *a, double *inv) {
+  double m[3][6];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      m[i][j] = a[3 * i + j];
+      m[i][3 + j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < 3; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (fabs(m[r][c]) > fabs(m[p][c])) p = r;
+    if (m[p][c] == 0.0) return 0;
+    if (p != c)
+      for (int j = 0; j < 6; ++j) { double t = m[c][j]; m[c][j] = m[p][j]; m[p][j] = t; }
+    double piv = m[c][c];
+    for (int j = 0; j < 6; ++j) m[c][j] /= piv;
+    for (int r = 0; r < 3; ++r) {
+      if (r == c) continue;
+      double f = m[r][c];
+      for (int j = 0; j < 6; ++j) m[r][j] -= f * m[c][j];
+    }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) inv[3 * i + j] = m[i][3 + j];
+  return 1;
+}
+
+/* Eigen-decomposition of a symmetric 3x3 matrix by the cyclic Jacobi method
+   (Golub and Van Loan, Matrix Computations, Sec. 8.5): rotations in the
+   planes (0,1), (0,2), (1,2) until the off-diagonal part is negligible.
+   On return a is diagonal (the eigenvalues) and the columns of v are the
+   eigenvectors. */
+static void sym3_jacobi(double *a, double *v) {
+  for (int i = 0; i < 9; ++i) v[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, all = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      all += a[i] * a[i];
+      if (i % 4 != 0) off += a[i] * a[i];
+    }
+    if (off <= 1e-30 * all) break; /* off-diagonal norm below ~1e-15 of the whole */
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        double apq = a[3 * p + q];
+        if (apq == 0.0) continue;
+        /* the symmetric 2x2 Schur decomposition of rows/columns p, q */
+        double tau = (a[3 * q + q] - a[3 * p + p]) / (2.0 * apq);
+        double t = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                              : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        double J[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Jt[9], tmp[9];
+        J[3 * p + p] = c; J[3 * p + q] = s;
+        J[3 * q + p] = -s; J[3 * q + q] = c;
+        mat3_transpose(J, Jt);
+        mat3_mul(Jt, a, tmp);
+        mat3_mul(tmp, J, a);
+        mat3_mul(v, J, tmp);
+        memcpy(v, tmp, sizeof tmp);
+      }
+  }
+}
+
+/* The rotation nearest to F (see the readings above): eigenvectors V of
+   F^T F ordered by descending eigenvalue with det V = +1, u_1 and u_2 the
+   normalised (and orthogonalised) F v_1 and F v_2, u_3 = u_1 x u_2,
+   R = U V^T. Exported for the tests. */
+void orc_closest_rotation(const double *F, double *R) {
+  double Ft[9], S[9], V[9];
+  mat3_transpose(F, Ft);
+  mat3_mul(Ft, F, S);
+  sym3_jacobi(S, V);
+  double lam[3] = {S[0], S[4], S[8]};
+  int ord[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (lam[ord[j]] > lam[ord[i]]) { int t = ord[i]; ord[i] = ord[j]; ord[j] = t; }
+  double v[3][3]; /* v[k] = k-th eigenvector, descending eigenvalue */
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) v[k][d] = V[3 * d + ord[k]];
+  double det = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) -
+               v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
+               v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
+  if (det < 0.0)
+    for (int d = 0; d < 3; ++d) v[2][d] = -v[2][d];
+  double u[3][3];
+  for (int k = 0; k < 2; ++k)
+    for (int d = 0; d < 3; ++d)
+      u[k][d] = (F[3 * d] * v[k][0] + F[3 * d + 1] * v[k][1]) + F[3 * d + 2] * v[k][2];
+  double n0 = sqrt((u[0][0] * u[0][0] + u[0][1] * u[0][1]) + u[0][2] * u[0][2]);
+  if (!(n0 > 0.0)) { for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0; return; }
+  for (int d = 0; d < 3; ++d) u[0][d] /= n0;
+  double pr = (u[0][0] * u[1][0] + u[0][1] * u[1][1]) + u[0][2] * u[1][2];
+  for (int d = 0; d < 3; ++d) u[1][d] -= pr * u[0][d];
+  double n1 = sqrt((u[1][0] * u[1][0] + u[1][1] * u[1][1]) + u[1][2] * u[1][2]);
+  if (!(n1 > 0.0)) { for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0; return; }
+  for (int d = 0; d < 3; ++d) u[1][d] /= n1;
+  u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+  u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+  u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      R[3 * i + j] = (u[0][i] * v[0][j] + u[1][i] * v[1][j]) + u[2][i] * v[2][j];
+}
+
+/* Dm^-1 of a tet from its rest positions p[4][3]; 0 if Dm is singular. */
+static int arap_rest(const double *p0, const double *p1, const double *p2, const double *p3,
+                     double *dm_inv) {
+  double Dm[9];
+  for (int d = 0; d < 3; ++d) {
+    Dm[3 * d + 0] = p1[d] - p0[d];
+    Dm[3 * d + 1] = p2[d] - p0[d];
+    Dm[3 * d + 2] = p3[d] - p0[d];
+  }
+  return mat3_inverse(Dm, dm_inv);
+}
+
+/* C = |F - R|_F^2 and the four slot gradients g[4][3] of one ARAP row. */
+static double arap_eval(const double *dm_inv, const double *x0, const double *x1,
+                        const double *x2, const double *x3, double *g) {
+  double Ds[9], F[9], R[9], P[9], DmT[9], H[9];
+  for (int d = 0; d < 3; ++d) {
+    Ds[3 * d + 0] = x1[d] - x0[d];
+    Ds[3 * d + 1] = x2[d] - x0[d];
+    Ds[3 * d + 2] = x3[d] - x0[d];
+  }
+  mat3_mul(Ds, dm_inv, F);
+  orc_closest_rotation(F, R);
+  double c = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    double e = F[i] - R[i];
+    c += e * e;
+    P[i] = 2.0 * e;
+  }
+  mat3_transpose(dm_inv, DmT);
+  mat3_mul(P, DmT, H);
+  for (int k = 1; k <= 3; ++k)
+    for (int d = 0; d < 3; ++d) g[3 * k + d] = H[3 * d + (k - 1)];
+  for (int d = 0; d < 3; ++d) g[d] = -((g[3 + d] + g[6 + d]) + g[9 + d]);
+  return c;
+}
+
+/* test hook: C and gradient of one ARAP tet from rest[4][3] and x[4][3];
+   returns 0 for a singular rest shape */
+int orc_arap_eval(const double *rest, const double *x, double *C, double *g) {
+  double dm_inv[9];
+  if (!arap_rest(rest, rest + 3, rest + 6, rest + 9, dm_inv)) return 0;
+  *C = arap_eval(dm_inv, x, x + 3, x + 6, x + 9, g);
+  return 1;
+}
+
 /* Constraint value and gradient of one row (Eq. 3 inputs).
    Edge (i, j): C = |x_i - x_j| - L0, g_i = n, g_j = -n.
    Volume (a, b, c, d): V = e1.(e2 x e3)/6, C = V - V0,
-   g_b = (e2 x e3)/6, g_c = (e3 x e1)/6, g_d = (e1 x e2)/6, g_a = -(g_b + g_c + g_d). */
+   g_b = (e2 x e3)/6, g_c = (e3 x e1)/6, g_d = (e1 x e2)/6, g_a = -(g_b + g_c + g_d).
+   ARAP (a, b, c, d): C = |F - R|_F^2 (arap_eval). */
 static double eval_row(const orc_sim *s, int64_t r, const double *pos, double *g /* [4][3] */) {
   const int32_t *v = s->rv + 4 * r;
   for (int k = 0; k < 12; ++k) g[k] = 0.0;
+  if (s->arap[r])
+    return arap_eval(s->dm_inv + 9 * r, pos + 3 * (int64_t)v[0], pos + 3 * (int64_t)v[1],
+                     pos + 3 * (int64_t)v[2], pos + 3 * (int64_t)v[3], g);
   if (s->rk[r] == 2) {
     const double *xi = pos + 3 * (int64_t)v[0], *xj = pos + 3 * (int64_t)v[1];
     double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
@@ -314,15 +507,18 @@ void orc_sim_free(orc_sim *s);
 orc_sim *orc_sim_create(int64_t n_verts, const double *rest, const double *inv_mass,
                         int64_t n_tets, const int32_t *tets, int64_t n_edges,
                         const int32_t *edges, int64_t n_vols, const int32_t *vol_tet,
+                        int64_t n_arap, const int32_t *arap_tet,
                         const double *alpha, double dt, double gx, double gy, double gz,
                         const orc_opts *opts, int *status) {
   *status = ORC_E_INVALID;
-  if (dt <= 0.0 || n_verts <= 0 || n_edges < 0 || n_vols < 0 || n_tets < 0) return NULL;
+  if (dt <= 0.0 || n_verts <= 0 || n_edges < 0 || n_vols < 0 || n_arap < 0 || n_tets < 0)
+    return NULL;
   orc_sim *s = calloc(1, sizeof *s);
   if (!s) { *status = ORC_E_NOMEM; return NULL; }
   if (opts) s->o = *opts; else orc_default_opts(&s->o);
   s->n_verts = n_verts; s->n_tets = n_tets; s->n_edges = n_edges; s->n_vols = n_vols;
-  s->m = n_edges + n_vols;
+  s->n_arap = n_arap;
+  s->m = n_edges + n_vols + n_arap;
   s->dt = dt; s->g[0] = gx; s->g[1] = gy; s->g[2] = gz;
   int64_t m = s->m;
   s->rest = malloc(sizeof(double) * 3 * n_verts);
@@ -330,13 +526,16 @@ orc_sim *orc_sim_create(int64_t n_verts, const double *rest, const double *inv_m
   s->tets = malloc(sizeof(int32_t) * 4 * (n_tets ? n_tets : 1));
   s->rv = malloc(sizeof(int32_t) * 4 * (m ? m : 1));
   s->rk = malloc(sizeof(int) * (m ? m : 1));
+  s->arap = calloc(m ? m : 1, sizeof(int));
+  s->dm_inv = calloc(9 * (m ? m : 1), sizeof(double));
   s->rest_c = malloc(sizeof(double) * (m ? m : 1));
   s->alpha_t = malloc(sizeof(double) * (m ? m : 1));
   s->lambda = calloc(m ? m : 1, sizeof(double));
   s->C = calloc(m ? m : 1, sizeof(double));
   s->grad = calloc(12 * (m ? m : 1), sizeof(double));
   s->b_last = calloc(m ? m : 1, sizeof(double));
-  if (!s->rest || !s->w || !s->tets || !s->rv || !s->rk || !s->rest_c || !s->alpha_t ||
+  if (!s->rest || !s->w || !s->tets || !s->rv || !s->rk || !s->arap || !s->dm_inv ||
+      !s->rest_c || !s->alpha_t ||
       !s->lambda || !s->C || !s->grad || !s->b_last) { orc_sim_free(s); *status = ORC_E_NOMEM; return NULL; }
   memcpy(s->rest, rest, sizeof(double) * 3 * n_verts);
   memcpy(s->w, inv_mass, sizeof(double) * n_verts);
@@ -369,10 +568,40 @@ orc_sim *orc_sim_create(int64_t n_verts, const double *rest, const double *inv_m
         if (s->rv[4 * r + a] == s->rv[4 * r + b]) { orc_sim_free(s); return NULL; }
     s->rk[r] = 4;
   }
+  for (int64_t q = 0; q < n_arap; ++q) {
+    int32_t t = arap_tet[q];
+    if (t < 0 || t >= n_tets) { orc_sim_free(s); return NULL; }
+    int64_t r = n_edges + n_vols + q;
+    for (int k = 0; k < 4; ++k) {
+      int32_t v = tets[4 * (int64_t)t + k];
+      if (v < 0 || v >= n_verts) { orc_sim_free(s); return NULL; }
+      s->rv[4 * r + k] = v;
+    }
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (s->rv[4 * r + a] == s->rv[4 * r + b]) { orc_sim_free(s); return NULL; }
+    s->rk[r] = 4;
+    s->arap[r] = 1;
+  }
   for (int64_t r = 0; r < m; ++r) {
     if (!(alpha[r] >= 0.0) || !isfinite(alpha[r])) { orc_sim_free(s); return NULL; }
     s->alpha_t[r] = alpha[r] / dt2;
     double g[12];
+    if (s->arap[r]) {
+      /* rest shape: Dm^-1, and a positive rest volume (positively oriented tet) */
+      const int32_t *v = s->rv + 4 * r;
+      const double *p0 = rest + 3 * (int64_t)v[0], *p1 = rest + 3 * (int64_t)v[1];
+      const double *p2 = rest + 3 * (int64_t)v[2], *p3 = rest + 3 * (int64_t)v[3];
+      double e1[3], e2[3], e3[3];
+      for (int d = 0; d < 3; ++d) { e1[d] = p1[d] - p0[d]; e2[d] = p2[d] - p0[d]; e3[d] = p3[d] - p0[d]; }
+      double vol6 = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                    e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+      if (!(vol6 > 0.0) || !arap_rest(p0, p1, p2, p3, s->dm_inv + 9 * r)) {
+        orc_sim_free(s); return NULL;
+      }
+      s->rest_c[r] = 0.0;
+      continue;
+    }
     s->rest_c[r] = eval_row(s, r, rest, g);
     if (!(s->rest_c[r] > 0.0)) { orc_sim_free(s); return NULL; } /* zero edge / inverted tet */
   }
@@ -1174,6 +1403,7 @@ done:
 void orc_sim_free(orc_sim *s) {
   if (!s) return;
   free(s->rest); free(s->w); free(s->tets); free(s->rv); free(s->rk); free(s->rest_c);
+  free(s->arap); free(s->dm_inv);
   free(s->alpha_t); free(s->lambda); free(s->C); free(s->grad); free(s->b_last);
   free(s->vc_ptr); free(s->vc_row); free(s->vc_slot);
   csr_free(&s->A);

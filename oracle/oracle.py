@@ -53,9 +53,13 @@ def lib():
         L.orc_mix64.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         L.orc_sim_create.restype = P
         L.orc_sim_create.argtypes = [C.c_int64, P, P, C.c_int64, P, C.c_int64, P, C.c_int64, P,
+                                     C.c_int64, P,
                                      P, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.POINTER(Opts), C.POINTER(C.c_int)]
         L.orc_sim_free.argtypes = [P]
+        L.orc_closest_rotation.argtypes = [P, P]
+        L.orc_arap_eval.restype = C.c_int
+        L.orc_arap_eval.argtypes = [P, P, P, P]
         L.orc_sim_rows.restype = C.c_int64
         L.orc_sim_rows.argtypes = [P]
         L.orc_sim_nnz.restype = C.c_int64
@@ -220,12 +224,14 @@ class Sim:
                       np.ascontiguousarray(w.tets, np.int32),
                       np.ascontiguousarray(w.edges, np.int32),
                       np.ascontiguousarray(w.vol_tet, np.int32),
+                      np.ascontiguousarray(w.arap_tet, np.int32),
                       np.ascontiguousarray(w.alpha, np.float64)]
-        rest, im, tets, edges, vt, al = self._keep
+        rest, im, tets, edges, vt, at, al = self._keep
         st = C.c_int(0)
         g = w.gravity
         self.s = lib().orc_sim_create(rest.shape[0], _p(rest), _p(im), tets.shape[0], _p(tets),
-                                      edges.shape[0], _p(edges), vt.shape[0], _p(vt), _p(al),
+                                      edges.shape[0], _p(edges), vt.shape[0], _p(vt),
+                                      at.shape[0], _p(at), _p(al),
                                       w.dt, g[0], g[1], g[2], C.byref(self.opts), C.byref(st))
         if not self.s:
             raise OracleError(st.value, "orc_sim_create")
@@ -321,3 +327,22 @@ def color(rowptr, col, prio):
 def positions(w):
     """[N,3] copies of the workload's initial positions and velocities."""
     return np.ascontiguousarray(w.x0.copy()), np.ascontiguousarray(w.v0.copy())
+
+
+def closest_rotation(F):
+    """The rotation nearest to the 3x3 matrix F (oracle's ARAP reading)."""
+    F = np.ascontiguousarray(F, np.float64).reshape(3, 3)
+    R = np.zeros((3, 3))
+    lib().orc_closest_rotation(_p(F), _p(R))
+    return R
+
+
+def arap_eval(rest, x):
+    """C = |F - R|_F^2 and its gradient [4, 3] for one tet (rest, x: [4, 3])."""
+    rest = np.ascontiguousarray(rest, np.float64).reshape(4, 3)
+    x = np.ascontiguousarray(x, np.float64).reshape(4, 3)
+    c = C.c_double(0.0)
+    g = np.zeros((4, 3))
+    if not lib().orc_arap_eval(_p(rest), _p(x), C.byref(c), _p(g)):
+        raise OracleError(1, "orc_arap_eval: singular rest shape")
+    return c.value, g

@@ -55,7 +55,7 @@ class Workload:
     tets: np.ndarray          # [T, 4] int32, positively oriented
     edges: np.ndarray         # [E, 2] int32, i < j, lexicographic
     vol_tet: np.ndarray       # [V] int32 tet indices carrying a volume constraint
-    alpha: np.ndarray         # [E + V] float64 compliance per constraint row
+    alpha: np.ndarray         # [E + V + A] float64 compliance per constraint row
     dt: float
     gravity: tuple
     x0: np.ndarray            # [N, 3] float64 initial positions
@@ -63,6 +63,8 @@ class Workload:
     frames: int = 1
     iters: int = 20
     info: dict = field(default_factory=dict)
+    # [A] int32 tet indices carrying an ARAP constraint (rows after the volumes)
+    arap_tet: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
 
     @property
     def n_verts(self) -> int:
@@ -70,7 +72,7 @@ class Workload:
 
     @property
     def n_rows(self) -> int:
-        return int(self.edges.shape[0] + self.vol_tet.shape[0])
+        return int(self.edges.shape[0] + self.vol_tet.shape[0] + self.arap_tet.shape[0])
 
 
 # --------------------------------------------------------------------------
@@ -151,6 +153,25 @@ def beam(nx: int, ny: int, nz: int, *, seed: int, volumes: bool, alpha_edge: flo
                     info={"grid": (nx, ny, nz), "h": h})
 
 
+def arap_beam(nx: int, ny: int, nz: int, *, seed: int, mu: float = 1e9, dt: float = 0.01,
+              squash: float = 0.3, jitter_frac: float = 1e-3, name: str = "arap_beam") -> Workload:
+    """Soft-body beam with one ARAP row per tet (no edge or volume rows): the
+    lattice and pinning of ``beam``, compliance 1 / (mu V_rest) per tet, and an
+    initial state squashed by ``squash`` along the long axis towards the pinned
+    x = 0 face, at rest velocity, which the constraints then restore."""
+    b = beam(nx, ny, nz, seed=seed, volumes=False, alpha_edge=0.0, dt=dt,
+             jitter_frac=jitter_frac, name=name)
+    vol = tet_volumes(b.rest, b.tets)
+    assert (vol > 0).all(), "jitter inverted a tet"
+    x0 = b.rest.copy()
+    x0[:, 0] *= 1.0 - squash
+    return Workload(name=name, rest=b.rest, inv_mass=b.inv_mass, tets=b.tets,
+                    edges=np.zeros((0, 2), np.int32), vol_tet=np.zeros(0, np.int32),
+                    alpha=1.0 / (mu * vol), dt=dt, gravity=b.gravity, x0=x0,
+                    v0=np.zeros_like(x0), arap_tet=np.arange(b.tets.shape[0], dtype=np.int32),
+                    info={"grid": (nx, ny, nz), "h": b.info["h"], "mu": mu, "squash": squash})
+
+
 def ellipsoid(nx: int, ny: int, nz: int, *, seed: int, semi=(0.5, 0.5, 1.0),
               density: float = 1000.0, jitter_cells: float = 0.2,
               name: str = "ellipsoid") -> Workload:
@@ -211,6 +232,22 @@ def beam_c1(seed: int = BASE_SEED + 1) -> Workload:
     """32x32x128 cube beam, edges (1e-9) + volumes (1e-10), 10 frames x 20 iterations."""
     w = beam(128, 32, 32, seed=seed, volumes=True, alpha_edge=1e-9, alpha_vol=1e-10,
              name="beam_32x32x128_edges_volumes")
+    w.frames, w.iters = 10, 20
+    return w
+
+
+def arap_a0(seed: int = BASE_SEED + 10) -> Workload:
+    """8x8x32 ARAP beam (12,288 tet rows), mu 1e9, dt 10 ms, squashed 30%,
+    1 frame x 20 iterations (the material of the paper's soft-body scenes)."""
+    w = arap_beam(32, 8, 8, seed=seed, name="arap_beam_8x8x32")
+    w.frames, w.iters = 1, 20
+    return w
+
+
+def arap_a1(seed: int = BASE_SEED + 11) -> Workload:
+    """32x32x128 ARAP beam (786,432 tet rows), mu 1e9, dt 10 ms, squashed 30%,
+    frames of 20 iterations."""
+    w = arap_beam(128, 32, 32, seed=seed, name="arap_beam_32x32x128")
     w.frames, w.iters = 10, 20
     return w
 
@@ -284,4 +321,4 @@ def perturbed(w: Workload, amp: float, seed: int = 99) -> Workload:
     return v
 
 
-CONFIGS = {"C0": beam_c0, "C1": beam_c1, "C2": muscle_c2}
+CONFIGS = {"C0": beam_c0, "C1": beam_c1, "C2": muscle_c2, "A0": arap_a0, "A1": arap_a1}

@@ -1,0 +1,232 @@
+"""Pins of the oracle's ARAP constraint (Sec. 6, As-Rigid-As-Possible
+constraints): C = |F - R|_F^2 per tet, F the deformation gradient, R its
+nearest rotation. Each check rests on something other than the oracle: a
+library polar decomposition or SVD, closed forms, invariances, brute-force
+minimality and finite differences.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+from oracle import oracle as O
+from paper_2505_13390_amd import workloads as W
+from tests.test_oracle_pins import dense, fd_jacobian
+
+UNIT = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+def rot(axis, angle):
+    """Rotation matrix from an axis and an angle (Rodrigues, via expm)."""
+    a = np.asarray(axis, np.float64)
+    a = a / np.linalg.norm(a) * angle
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return sl.expm(K)
+
+
+def random_rest(rng):
+    """A positively oriented, reasonably shaped tet."""
+    while True:
+        p = UNIT + 0.2 * rng.standard_normal((4, 3))
+        D = (p[1:] - p[0]).T
+        if np.linalg.det(D) > 0.05:
+            return p
+
+
+def deform(rest, F, t=(0.0, 0.0, 0.0)):
+    """Positions of the tet under the affine map x -> F x + t."""
+    return rest @ np.asarray(F).T + np.asarray(t)
+
+
+def signed_svd_rotation(F):
+    """Nearest rotation from numpy's SVD: U diag(1, 1, det(U V^T)) V^T."""
+    U, _, Vt = np.linalg.svd(F)
+    d = np.sign(np.linalg.det(U @ Vt))
+    return U @ np.diag([1.0, 1.0, d]) @ Vt
+
+
+# ------------------------------------------------------------ nearest rotation
+def test_nearest_rotation_is_the_polar_factor():
+    """det F > 0: R equals the orthogonal polar factor (scipy) to rounding,
+    from near-identity to strongly stretched F."""
+    rng = np.random.default_rng(11)
+    for k in range(300):
+        scale = [0.01, 0.3, 1.0][k % 3]
+        F = np.eye(3) + scale * rng.standard_normal((3, 3))
+        if np.linalg.det(F) <= 0:
+            continue
+        U, _ = sl.polar(F)
+        R = O.closest_rotation(F)
+        cond = np.linalg.cond(F)
+        assert np.abs(R - U).max() <= 1e-13 * cond, (k, cond)
+
+
+def test_nearest_rotation_of_inverted_matrix_is_signed_svd():
+    """det F < 0: R is the rotation U diag(1,1,-1) V^T (not the reflection the
+    polar factor would give), and no nearby rotation is closer to F."""
+    rng = np.random.default_rng(12)
+    for k in range(100):
+        F = rng.standard_normal((3, 3))
+        if np.linalg.det(F) >= 0:
+            F[:, 0] = -F[:, 0]
+        sv = np.linalg.svd(F, compute_uv=False)
+        if sv[1] - sv[2] < 1e-3 or sv[2] < 1e-3:
+            continue   # keep the minimiser unique and well separated
+        R = O.closest_rotation(F)
+        assert abs(np.linalg.det(R) - 1.0) <= 1e-12
+        assert np.abs(R @ R.T - np.eye(3)).max() <= 1e-12
+        assert np.abs(R - signed_svd_rotation(F)).max() <= 1e-10 * np.linalg.cond(F)
+        best = ((F - R) ** 2).sum()
+        for j in range(200):
+            Q = R @ rot(rng.standard_normal(3), 0.05 * rng.random())
+            assert ((F - Q) ** 2).sum() >= best - 1e-13
+
+
+def test_nearest_rotation_reading_for_rank_one():
+    """Not unique when rank(F) <= 1: the reading takes R = I."""
+    F = np.outer([1.0, 2.0, 0.5], [0.3, -1.0, 2.0])
+    assert np.array_equal(O.closest_rotation(F), np.eye(3))
+    assert np.array_equal(O.closest_rotation(np.zeros((3, 3))), np.eye(3))
+
+
+# ------------------------------------------------------------- constraint value
+def test_rest_and_rigid_motions_give_zero():
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        rest = random_rest(rng)
+        c, g = O.arap_eval(rest, rest)
+        assert c <= 1e-28 and np.abs(g).max() <= 1e-13
+        Q = rot(rng.standard_normal(3), rng.uniform(0, np.pi))
+        c, g = O.arap_eval(rest, deform(rest, Q, rng.standard_normal(3)))
+        assert c <= 1e-26 and np.abs(g).max() <= 1e-12
+
+
+def test_closed_forms_in_the_singular_values():
+    """C = sum (s_i - 1)^2 over the signed singular values: uniform scale,
+    rotated stretches, and an inverted element (one negative value)."""
+    rng = np.random.default_rng(14)
+    rest = random_rest(rng)
+    for s in [0.5, 0.9, 1.3, 2.0]:
+        c, _ = O.arap_eval(rest, deform(rest, s * np.eye(3)))
+        assert c == pytest.approx(3 * (s - 1) ** 2, rel=1e-13)
+    for _ in range(20):
+        sig = rng.uniform(0.3, 2.5, 3)
+        P = rot(rng.standard_normal(3), rng.uniform(0, np.pi))
+        Q = rot(rng.standard_normal(3), rng.uniform(0, np.pi))
+        F = P @ np.diag(sig) @ Q.T
+        c, _ = O.arap_eval(rest, deform(rest, F))
+        assert c == pytest.approx(((sig - 1) ** 2).sum(), rel=1e-11, abs=1e-14)
+    # inverted: signed values (2, 1.5, -0.5) -> 1 + 0.25 + 2.25
+    c, _ = O.arap_eval(rest, deform(rest, np.diag([2.0, 1.5, -0.5])))
+    assert c == pytest.approx(3.5, rel=1e-13)
+
+
+def test_uniform_scale_gradient_closed_form():
+    """F = s I: R = I, dC/dF = 2 (s - 1) I, so dC/dx_i is column i - 1 of
+    2 (s - 1) Dm^-T (Dm^-1 from numpy), slot 0 the negated sum."""
+    rng = np.random.default_rng(15)
+    rest = random_rest(rng)
+    s = 1.25
+    _, g = O.arap_eval(rest, deform(rest, s * np.eye(3)))
+    Dm = (rest[1:] - rest[0]).T
+    H = 2 * (s - 1) * np.linalg.inv(Dm).T
+    for i in range(1, 4):
+        assert np.allclose(g[i], H[:, i - 1], rtol=1e-12, atol=1e-13)
+    assert np.allclose(g[0], -H.sum(axis=1), rtol=1e-12, atol=1e-13)
+
+
+def test_gradient_matches_finite_differences():
+    """Central differences of C over all 12 coordinates, including inverted
+    configurations."""
+    rng = np.random.default_rng(16)
+    h = 1e-6
+    for k in range(25):
+        rest = random_rest(rng)
+        F = np.eye(3) + 0.5 * rng.standard_normal((3, 3))
+        if k % 5 == 0:
+            F[:, 2] = -F[:, 2]
+        sv = np.linalg.svd(F, compute_uv=False)
+        if sv[2] < 0.05 or sv[1] - sv[2] < 0.05:
+            continue
+        x = deform(rest, F) + 0.05 * rng.standard_normal((4, 3))
+        _, g = O.arap_eval(rest, x)
+        fd = np.zeros((4, 3))
+        for i in range(4):
+            for d in range(3):
+                xp = x.copy(); xp[i, d] += h
+                xm = x.copy(); xm[i, d] -= h
+                fd[i, d] = (O.arap_eval(rest, xp)[0] - O.arap_eval(rest, xm)[0]) / (2 * h)
+        assert np.abs(fd - g).max() <= 1e-7 * max(1.0, np.abs(g).max()), k
+
+
+def test_rotation_and_translation_equivariance():
+    """C(Q x + t) = C(x) and grad(Q x + t) = Q grad(x); the slot gradients
+    sum to zero (translation invariance)."""
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        rest = random_rest(rng)
+        x = deform(rest, np.eye(3) + 0.4 * rng.standard_normal((3, 3)))
+        c, g = O.arap_eval(rest, x)
+        Q = rot(rng.standard_normal(3), rng.uniform(0, np.pi))
+        c2, g2 = O.arap_eval(rest, x @ Q.T + rng.standard_normal(3))
+        assert c2 == pytest.approx(c, rel=1e-11, abs=1e-14)
+        assert np.abs(g2 - g @ Q.T).max() <= 1e-11 * max(1.0, np.abs(g).max())
+        assert np.abs(g.sum(axis=0)).max() <= 1e-13 * max(1.0, np.abs(g).max())
+
+
+# ------------------------------------------------------- ARAP rows in the system
+def tiny_arap(dims=(2, 1, 1), squash=0.2, mu=1e6):
+    return W.arap_beam(*dims, seed=5, mu=mu, squash=squash, name="tiny_arap")
+
+
+def test_arap_rows_in_the_system_matrix():
+    """A = gradC M^-1 gradC^T + alpha/dt^2 with gradC from finite differences
+    of the oracle's own constraint values, alpha = 1/(mu V_rest); b = -C;
+    A symmetric positive definite."""
+    w = tiny_arap()
+    s = O.Sim(w)
+    val, b = s.assemble(w.x0)
+    rp, col = s.pattern()
+    A = dense(rp, col, val)
+    Jfd = fd_jacobian(s, w.x0)
+    Minv = np.repeat(w.inv_mass, 3)
+    Aref = Jfd @ np.diag(Minv) @ Jfd.T + np.diag(w.alpha / w.dt ** 2)
+    assert np.abs(A - Aref).max() <= 1e-6 * np.abs(Aref).max()
+    vol = W.tet_volumes(w.rest, w.tets)
+    assert np.allclose(w.alpha, 1.0 / (w.info["mu"] * vol), rtol=1e-15)
+    C, _ = s.constraints(w.x0)
+    assert np.array_equal(b, -C)
+    # squashed by 20% along x: F ~ diag(0.8, 1, 1), C ~ 0.04 per tet
+    assert np.allclose(C, 0.04, rtol=0.05)
+    assert np.array_equal(A, A.T)
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+def test_arap_rest_state_stays_at_rest():
+    """At the rest shape C and its gradient vanish up to rounding, so a frame
+    without gravity moves nothing beyond rounding."""
+    w = tiny_arap(squash=0.0)
+    w.gravity = (0.0, 0.0, 0.0)
+    s = O.Sim(w)
+    pos, vel = O.positions(w)
+    r = s.step(pos, vel, 3)
+    assert r["status"] == 0
+    assert np.abs(pos - w.rest).max() <= 1e-12
+    assert np.abs(r["bnorm"]).max() <= 1e-25
+
+
+def test_arap_frame_restores_the_squashed_shape():
+    """A squashed stiff beam with the full position update (omega = 1 in the
+    last step of each global iteration): the iterations drive |b| = |C +
+    alpha~ lambda| down by more than an order of magnitude within one frame,
+    and C itself falls. With the lazily reused Jacobi weight the V-cycle needs
+    the wider lambda_max margin (1.5) that the ARAP workloads use."""
+    w = W.arap_beam(16, 4, 4, seed=21, mu=1e9, squash=0.3, name="arap_16x4x4")
+    w.gravity = (0.0, 0.0, 0.0)
+    s = O.Sim(w, O.default_opts(omega_relax=1.0, lmax_scale=1.5))
+    pos, vel = O.positions(w)
+    c0 = np.linalg.norm(s.constraints(pos)[0])
+    r = s.step(pos, vel, 20)
+    assert r["status"] == 0
+    c1 = np.linalg.norm(s.constraints(pos)[0])
+    assert r["bnorm"][-1] <= 0.05 * r["bnorm"][0], r["bnorm"]
+    assert c1 <= 0.5 * c0, (c0, c1)

@@ -50,7 +50,13 @@ def grad_matrix(sim, w, g):
     m = sim.m
     J = np.zeros((m, 3 * w.n_verts))
     for r in range(m):
-        vs = w.edges[r] if r < w.edges.shape[0] else w.tets[w.vol_tet[r - w.edges.shape[0]]]
+        ne, nvol = w.edges.shape[0], w.vol_tet.shape[0]
+        if r < ne:
+            vs = w.edges[r]
+        elif r < ne + nvol:
+            vs = w.tets[w.vol_tet[r - ne]]
+        else:
+            vs = w.tets[w.arap_tet[r - ne - nvol]]
         for k, v in enumerate(vs):
             J[r, 3 * v:3 * v + 3] += g[r, k]
     return J
