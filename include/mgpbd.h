@@ -109,13 +109,21 @@ typedef struct {
 } mgpbd_mesh;
 
 /* Constraint rows. Row order: the n_edges distance constraints, then the
-   n_vols volume constraints. edges: [n_edges][2], i < j, strictly ascending
-   lexicographic; vol_tet: indices into mesh tets. All arrays host. */
+   n_vols volume constraints, then the n_arap ARAP constraints. edges:
+   [n_edges][2], i < j, strictly ascending lexicographic; vol_tet and
+   arap_tet: indices into mesh tets. All arrays host.
+   An ARAP row (Sec. 6, As-Rigid-As-Possible constraints) is
+   C = |F - R|_F^2 for its tet, F = Ds Dm^-1 the deformation gradient
+   (Ds = [x1 - x0, x2 - x0, x3 - x0], Dm the same at rest) and R the rotation
+   (det +1) nearest to F; target C = 0. The paper takes its compliance as
+   1 / (mu V_rest), mu the second Lame parameter. */
 typedef struct {
   int64_t n_edges;
   const int32_t *edges;
   int64_t n_vols;
   const int32_t *vol_tet;
+  int64_t n_arap;
+  const int32_t *arap_tet;
 } mgpbd_constraints;
 
 /* A caller-supplied symmetric positive definite matrix in CSR form, device
@@ -161,7 +169,8 @@ typedef struct mgpbd_batch mgpbd_batch;
 void mgpbd_default_options(mgpbd_options *opt);
 
 /* Create a simulation context for one body (Algorithm 1 inputs: mesh,
-   constraints, per-row compliance alpha (host, [n_edges + n_vols], >= 0),
+   constraints, per-row compliance alpha (host, [n_edges + n_vols + n_arap],
+   >= 0),
    time step dt > 0, gravity (host [3]) as the external acceleration of the
    semi-implicit Euler predict). Copies everything to library-owned device
    memory and builds the fixed pattern of A (pairs of rows that share a vertex,

@@ -40,7 +40,7 @@ class Mesh(C.Structure):
 
 class Constraints(C.Structure):
     _fields_ = [("n_edges", C.c_int64), ("edges", C.c_void_p), ("n_vols", C.c_int64),
-                ("vol_tet", C.c_void_p)]
+                ("vol_tet", C.c_void_p), ("n_arap", C.c_int64), ("arap_tet", C.c_void_p)]
 
 
 class Csr(C.Structure):
@@ -168,19 +168,21 @@ def _prepare(ctx):
 
 
 def mgpbd_create(rest, inv_mass, tets, edges, vol_tet, compliance, dt, gravity,
-                 opt: Options | None = None):
-    """Create a body context from host arrays (numpy). Returns the handle."""
+                 opt: Options | None = None, arap_tet=None):
+    """Create a body context from host arrays (numpy). Returns the handle.
+    Rows: edges, then volume rows (vol_tet), then ARAP rows (arap_tet)."""
     rest = np.ascontiguousarray(rest, np.float64)
     inv_mass = np.ascontiguousarray(inv_mass, np.float64)
     tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
     edges = np.ascontiguousarray(edges, np.int32).reshape(-1, 2)
     vol_tet = np.ascontiguousarray(vol_tet, np.int32)
+    arap_tet = np.ascontiguousarray(np.zeros(0) if arap_tet is None else arap_tet, np.int32)
     comp = np.ascontiguousarray(compliance, np.float64)
     grav = np.ascontiguousarray(gravity, np.float64)
     mesh = Mesh(rest.shape[0], _np_ptr(rest).value, _np_ptr(inv_mass).value, tets.shape[0],
                 _np_ptr(tets).value)
     cons = Constraints(edges.shape[0], _np_ptr(edges).value, vol_tet.shape[0],
-                       _np_ptr(vol_tet).value)
+                       _np_ptr(vol_tet).value, arap_tet.shape[0], _np_ptr(arap_tet).value)
     h = C.c_void_p()
     st = lib().mgpbd_create(C.byref(mesh), C.byref(cons), _np_ptr(comp), float(dt),
                             _np_ptr(grav), C.byref(opt) if opt is not None else None, C.byref(h))
@@ -387,7 +389,7 @@ class Body:
         import torch
         self.w = w
         self.ctx = mgpbd_create(w.rest, w.inv_mass, w.tets, w.edges, w.vol_tet, w.alpha, w.dt,
-                                w.gravity, opt)
+                                w.gravity, opt, arap_tet=w.arap_tet)
         self.m, self.nnz = mgpbd_num_rows(self.ctx)
         t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
         self.x = [t(w.x0[:, k]) for k in range(3)]

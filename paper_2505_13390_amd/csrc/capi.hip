@@ -44,11 +44,16 @@ struct mgpbd_ctx {
   DevBuf<int8_t> vslot;
   DevBuf<double> w, alpha_t, rest_c, C, grad, lambda, b, old[3];
   DevBuf<int> bad;
+  // ARAP rows (absent without them): kind[r] = 1 marks one, dm_inv[r] holds
+  // the inverse rest shape matrix of its tet
+  bool has_arap = false;
+  DevBuf<int8_t> kind;
+  DevBuf<double> dm_inv;
   // matrix-free fine operator: positions of the current iteration, the
   // per-incidence gradients and the gather scratch (FP64; FP32 copies for the
   // mixed V-cycle)
   DevBuf<double> mf_pos, mf_gT, mf_u;
-  DevBuf<float> mf_pos32, mf_gT32, mf_u32, mf_alpha32, mf_w32;
+  DevBuf<float> mf_pos32, mf_gT32, mf_u32, mf_alpha32, mf_w32, mf_g32;
   std::vector<int32_t> force;
   bool have_rhs = false;
   bool batch_owned = false;   // the system context of a batch (freed with it)
@@ -153,6 +158,10 @@ void alloc_state(mgpbd_ctx *c) {
     v.m = c->m; v.nv = c->nv; v.rv = c->rv.p; v.pos = c->mf_pos.p; v.alpha = c->alpha_t.p;
     v.vptr = c->vptr.p; v.vrow = c->vrow.p; v.gT = c->mf_gT.p; v.w = c->w.p;
     v.u = c->mf_u.p;
+    if (c->has_arap) {
+      v.kind = c->kind.p;
+      v.gst = c->grad.p;
+    }
     S.mf = v;
     if (S.mixed()) {
       c->mf_pos32.alloc(nv4);
@@ -166,6 +175,11 @@ void alloc_state(mgpbd_ctx *c) {
       f.m = c->m; f.nv = c->nv; f.rv = c->rv.p; f.pos = c->mf_pos32.p;
       f.alpha = c->mf_alpha32.p; f.vptr = c->vptr.p; f.vrow = c->vrow.p; f.gT = c->mf_gT32.p;
       f.w = c->mf_w32.p; f.u = c->mf_u32.p;
+      if (c->has_arap) {
+        c->mf_g32.alloc(12 * (size_t)c->m);
+        f.kind = c->kind.p;
+        f.gst = c->mf_g32.p;
+      }
       S.mf32 = f;
     }
   }
@@ -205,14 +219,18 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
   std::vector<int32_t> fv(nb, 0);
   int n_stopped = 0;
   for (int ite = 0; ite < n_iters && n_stopped < nb; ++ite) {
-    launch_constraints(m, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
+    const int8_t *kind = c->has_arap ? c->kind.p : nullptr;
+    launch_constraints(m, c->rv.p, kind, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
+    if (kind) launch_arap_constraints(m, c->rv.p, kind, c->dm_inv.p, xyz, c->C.p, c->grad.p, st);
     const int64_t n_inc = (int64_t)c->vrow.n;
     if (S.mf.ok())
       launch_mf_prepare<double>(nv, xyz[0], xyz[1], xyz[2], n_inc, c->vrow.p, c->vslot.p,
                                 c->grad.p, c->mf_pos.p, c->mf_gT.p, st);
-    if (S.mf32.ok())
+    if (S.mf32.ok()) {
       launch_mf_prepare<float>(nv, xyz[0], xyz[1], xyz[2], n_inc, c->vrow.p, c->vslot.p,
                                c->grad.p, c->mf_pos32.p, c->mf_gT32.p, st);
+      if (kind) launch_d2f(12 * m, c->grad.p, c->mf_g32.p, nullptr, st);
+    }
     launch_assemble(m, 16, F.rowptr.p, F.col.p, c->meta.p, c->rv.p, c->w.p, c->grad.p,
                     c->alpha_t.p, c->C.p, c->lambda.p, F.val.p, S.mixed() ? F.val32.p : nullptr,
                     c->b.p, st);
@@ -328,7 +346,7 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
   if (!mesh || !cons || !compliance || !gravity || !mesh->rest || !mesh->inv_mass)
     return MGPBD_E_INVALID_ARG;
   if ((mesh->n_tets && !mesh->tets) || (cons->n_edges && !cons->edges) ||
-      (cons->n_vols && !cons->vol_tet))
+      (cons->n_vols && !cons->vol_tet) || (cons->n_arap && !cons->arap_tet))
     return MGPBD_E_INVALID_ARG;
   auto *c = new (std::nothrow) mgpbd_ctx();
   if (!c) return MGPBD_E_OUT_OF_MEMORY;
@@ -346,7 +364,7 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
     }
     Topology t;
     build_topology(nv, mesh->n_tets, mesh->tets, cons->n_edges, cons->edges, cons->n_vols,
-                   cons->vol_tet, t);
+                   cons->vol_tet, cons->n_arap, cons->arap_tet, t);
     MG_REQUIRE(t.nnz < (int64_t)INT32_MAX, MGPBD_E_INVALID_ARG,
                "A has more than 2^31 entries; split the body into a batch");
     c->has_body = true;
@@ -374,6 +392,14 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
     Level &F = c->solver->L0();
     F.rowptr.upload(t.rowptr.data(), t.rowptr.size(), st);
     F.col.upload(t.col.data(), t.col.size(), st);
+    const int64_t arap_lo = t.n_edges + t.n_vols;
+    if (t.n_arap > 0) {
+      c->has_arap = true;
+      std::vector<int8_t> kind(t.m, 0);
+      for (int64_t r = arap_lo; r < t.m; ++r) kind[r] = 1;
+      c->kind.upload(kind.data(), t.m, st);
+      c->dm_inv.alloc(9 * (size_t)t.m);
+    }
     alloc_state(c);
     c->rest_c.alloc(t.m);
     // rest lengths and volumes: the constraint kernel itself at the rest
@@ -384,17 +410,29 @@ mgpbd_status mgpbd_create(const mgpbd_mesh *mesh, const mgpbd_constraints *cons,
       for (int64_t v = 0; v < nv; ++v) comp[v] = mesh->rest[3 * v + k];
       rx[k].upload(comp.data(), nv, st);
     }
+    // (ARAP rows keep rest_c = 0: their target is C = 0)
     launch_fill(t.m, 0.0, c->rest_c.p, st);
+    launch_fill(t.m, 0.0, c->C.p, st);
     double *xyz[3] = {rx[0].p, rx[1].p, rx[2].p};
-    launch_constraints(t.m, c->rv.p, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
+    const int8_t *kind = c->has_arap ? c->kind.p : nullptr;
+    launch_constraints(t.m, c->rv.p, kind, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
     MG_HIP(hipMemcpyAsync(c->rest_c.p, c->C.p, sizeof(double) * t.m, hipMemcpyDeviceToDevice, st));
     std::vector<double> rc(t.m);
     c->rest_c.download(rc.data(), t.m, st);
+    std::vector<double> det6;
+    if (kind) {
+      launch_arap_rest(t.m, c->rv.p, kind, xyz, c->dm_inv.p, c->C.p, st);
+      det6.resize(t.m);
+      c->C.download(det6.data(), t.m, st);
+    }
     MG_HIP(hipStreamSynchronize(st));
-    for (int64_t r = 0; r < t.m; ++r)
-      MG_REQUIRE(rc[r] > 0.0, MGPBD_E_INVALID_ARG,
-                 (r < t.n_edges ? "zero-length rest edge at row " : "non-positive rest volume at row ") +
+    for (int64_t r = 0; r < t.m; ++r) {
+      const bool ok = r < arap_lo ? rc[r] > 0.0 : det6[r] > 0.0;
+      MG_REQUIRE(ok, MGPBD_E_INVALID_ARG,
+                 (r < t.n_edges ? "zero-length rest edge at row "
+                                : "non-positive rest volume at row ") +
                      std::to_string(r));
+    }
   });
   if (s != MGPBD_OK) {
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -671,6 +709,11 @@ mgpbd_status mgpbd_batch_create(mgpbd_ctx *const *ctxs, int32_t n, mgpbd_batch *
     c->rest_c.alloc(c->m);
     F.rowptr.alloc(c->m + 1);
     F.col.alloc(c->nnz);
+    for (int k = 0; k < n; ++k) c->has_arap = c->has_arap || ctxs[k]->has_arap;
+    if (c->has_arap) {
+      c->kind.alloc(c->m);
+      c->dm_inv.alloc(9 * (size_t)c->m);
+    }
     auto d2d = [&](void *dst, const void *src, size_t bytes) {
       if (bytes) MG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
     };
@@ -688,6 +731,14 @@ mgpbd_status mgpbd_batch_create(mgpbd_ctx *const *ctxs, int32_t n, mgpbd_batch *
       d2d(c->w.p + v0, b.w.p, sizeof(double) * b.nv);
       d2d(c->alpha_t.p + r0, b.alpha_t.p, sizeof(double) * b.m);
       d2d(c->rest_c.p + r0, b.rest_c.p, sizeof(double) * b.m);
+      if (c->has_arap && b.m) {
+        if (b.has_arap) {
+          d2d(c->kind.p + r0, b.kind.p, b.m);
+          d2d(c->dm_inv.p + 9 * r0, b.dm_inv.p, sizeof(double) * 9 * b.m);
+        } else {
+          MG_HIP(hipMemsetAsync(c->kind.p + r0, 0, b.m, st));
+        }
+      }
     }
     MG_HIP(hipMemcpyAsync(F.rowptr.p + c->m, &eoff[n], sizeof(int64_t), hipMemcpyHostToDevice, st));
     MG_HIP(hipMemcpyAsync(c->vptr.p + c->nv, &toff[n], sizeof(int64_t), hipMemcpyHostToDevice, st));

@@ -94,12 +94,20 @@ __device__ __forceinline__ T dot_u(const T (&g)[3], const T *__restrict__ u) {
 // one at a time (the same expressions as tet_grads) and consumed at once,
 // which keeps the register count low enough for full occupancy.
 template <class T>
-__device__ __forceinline__ T mf_row(const MfView<T> &A, const int4 r) {
+__device__ __forceinline__ T mf_row(const MfView<T> &A, const int64_t c, const int4 r) {
   const T *__restrict__ pos = A.pos;
   const T *__restrict__ u = A.u;
   const int64_t va = r.x, vb = r.y;
   T s;
-  if (r.z < 0) {
+  if (A.kind && A.kind[c]) {   // stored gradients (same values the assembly read)
+    const T *g = A.gst + 12 * c;
+    T g0[3] = {g[0], g[1], g[2]}, g1[3] = {g[3], g[4], g[5]};
+    T g2[3] = {g[6], g[7], g[8]}, g3[3] = {g[9], g[10], g[11]};
+    s = dot_u(g0, u + 4 * va);
+    s += dot_u(g1, u + 4 * vb);
+    s += dot_u(g2, u + 4 * (int64_t)r.z);
+    s += dot_u(g3, u + 4 * (int64_t)r.w);
+  } else if (r.z < 0) {
     T g0[3], g1[3];
     edge_grads(pos + 4 * va, pos + 4 * vb, g0, g1);
     s = dot_u(g0, u + 4 * va);
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T
     const int4 r = rn;
     const int64_t cn = c + blockDim.x;
     if (cn < hi) rn = rv4[cn];
-    const T s = mf_row(A, r) + A.alpha[c] * x(c);
+    const T s = mf_row(A, c, r) + A.alpha[c] * x(c);
     op(c, s, acc);
   }
   if (partials) {

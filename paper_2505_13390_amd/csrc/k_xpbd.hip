@@ -35,11 +35,12 @@ void launch_predict(int64_t nv, const double *w, const double *g, double dt, dou
 // C and gradient of each row (formulas in grad.hpp): edge C = |x_i - x_j| - L0,
 // volume C = e1.(e2 x e3)/6 - V0.
 __global__ void k_constraints(int64_t m, const int32_t *__restrict__ rv,
+                              const int8_t *__restrict__ kind,
                               const double *__restrict__ rest_c, const double *__restrict__ x,
                               const double *__restrict__ y, const double *__restrict__ z,
                               double *__restrict__ C, double *__restrict__ grad) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
+  if (r >= m || (kind && kind[r])) return;
   const int32_t *v = rv + 4 * r;
   double g[4][3];
   double val;
@@ -67,10 +68,10 @@ __global__ void k_constraints(int64_t m, const int32_t *__restrict__ rv,
 #pragma unroll
     for (int d = 0; d < 3; ++d) go[3 * k + d] = g[k][d];
 }
-void launch_constraints(int64_t m, const int32_t *rv, const double *rest_c,
+void launch_constraints(int64_t m, const int32_t *rv, const int8_t *kind, const double *rest_c,
                         const double *const *xyz, double *C, double *grad, hipStream_t s) {
   if (m)
-    k_constraints<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, rv, rest_c, xyz[0], xyz[1],
+    k_constraints<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, rv, kind, rest_c, xyz[0], xyz[1],
                                                            xyz[2], C, grad);
 }
 

@@ -7,7 +7,8 @@
 // gradient of each incidence from a vertex-major copy; then a row pass
 // (A x)_c = sum_k g_{c,k} . u_{v_k} + alpha~_c x_c that recomputes the row's
 // gradients from the positions with the constraint kernel's own formulas
-// (grad.hpp), so it reads only the row's vertex ids from HBM. Both use
+// (grad.hpp), so it reads only the row's vertex ids from HBM (ARAP rows read
+// their stored gradients instead). Both use
 // exactly the gradients the assembly used. The assembled A is still built
 // every global iteration: the setup, the Galerkin products and the Jacobi
 // diagonal read it.
@@ -28,6 +29,11 @@ struct MfView {
   const T *gT = nullptr;          // [E][3] gradient of each incidence
   const T *w = nullptr;           // [nv] inverse masses
   T *u = nullptr;                 // [nv][4] scratch of the vertex gather
+  // rows whose gradients are read instead of recomputed (ARAP rows, whose
+  // nearest rotation is too costly to repeat per product): kind[c] != 0 marks
+  // them, gst[c][4][3] holds their gradients; both null without such rows
+  const int8_t *kind = nullptr;
+  const T *gst = nullptr;
   bool ok() const { return m > 0 && rv && pos && alpha && vptr && vrow && gT && w && u; }
 };
 

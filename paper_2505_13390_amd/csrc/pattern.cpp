@@ -29,13 +29,16 @@ void parallel_rows(int64_t m, F f) {
 }  // namespace
 
 void build_topology(int64_t n_verts, int64_t n_tets, const int32_t *tets, int64_t n_edges,
-                    const int32_t *edges, int64_t n_vols, const int32_t *vol_tet, Topology &t) {
+                    const int32_t *edges, int64_t n_vols, const int32_t *vol_tet,
+                    int64_t n_arap, const int32_t *arap_tet, Topology &t) {
   MG_REQUIRE(n_verts > 0 && n_verts < (int64_t)INT32_MAX, MGPBD_E_INVALID_ARG, "n_verts out of range");
-  MG_REQUIRE(n_edges >= 0 && n_vols >= 0 && n_tets >= 0, MGPBD_E_INVALID_ARG, "negative size");
+  MG_REQUIRE(n_edges >= 0 && n_vols >= 0 && n_arap >= 0 && n_tets >= 0, MGPBD_E_INVALID_ARG,
+             "negative size");
   t.n_verts = n_verts;
   t.n_edges = n_edges;
   t.n_vols = n_vols;
-  t.m = n_edges + n_vols;
+  t.n_arap = n_arap;
+  t.m = n_edges + n_vols + n_arap;
   const int64_t m = t.m;
   MG_REQUIRE(m < (int64_t)INT32_MAX, MGPBD_E_INVALID_ARG, "too many constraint rows");
   t.rv.assign(4 * (size_t)m, -1);
@@ -51,9 +54,12 @@ void build_topology(int64_t n_verts, int64_t n_tets, const int32_t *tets, int64_
     t.rv[4 * e] = i;
     t.rv[4 * e + 1] = j;
   }
-  for (int64_t q = 0; q < n_vols; ++q) {
-    int32_t tt = vol_tet[q];
-    MG_REQUIRE(tt >= 0 && tt < n_tets, MGPBD_E_INVALID_ARG, "vol_tet index out of range");
+  // tet rows: the volume rows, then the ARAP rows
+  for (int64_t q = 0; q < n_vols + n_arap; ++q) {
+    const bool vol = q < n_vols;
+    int32_t tt = vol ? vol_tet[q] : arap_tet[q - n_vols];
+    MG_REQUIRE(tt >= 0 && tt < n_tets, MGPBD_E_INVALID_ARG,
+               vol ? "vol_tet index out of range" : "arap_tet index out of range");
     int64_t r = n_edges + q;
     for (int k = 0; k < 4; ++k) {
       int32_t v = tets[4 * (int64_t)tt + k];
