@@ -33,14 +33,20 @@ def spmv_bytes(m: int, nnz: int) -> int:
     return 12 * nnz + 8 * (m + 1) + 8 * m + 8 * m
 
 
-def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int):
+def mf_bytes(m: int, nv: int, n_inc: int, n_edges: int, n_vols: int, n_arap: int = 0):
     """Algorithmic bytes of the two kernels of one matrix-free fine-level A p
     product (every array counted once). The vertex gather reads the incidence
     pointers, rows and gradients, the inverse masses and p, and writes u (4
     values per vertex); the row pass reads the row vertex ids, the positions
-    (its gradients are recomputed from them), u, alpha~ and p, and writes q."""
+    (edge and volume gradients are recomputed from them), the row kinds and
+    the stored gradients of ARAP rows (when there are any), u, alpha~ and p,
+    and writes q."""
     gather = 8 * (nv + 1) + 4 * n_inc + 24 * n_inc + 8 * nv + 8 * m + 32 * nv
-    rows = 16 * m + 32 * nv + 32 * nv + 8 * m + 8 * m + 8 * m
+    rows = 16 * m + 32 * nv + 8 * m + 8 * m + 8 * m
+    if n_edges + n_vols:
+        rows += 32 * nv
+    if n_arap:
+        rows += m + 96 * n_arap
     return gather, rows
 
 
@@ -73,13 +79,14 @@ MF_SOURCES = ("paper_2505_13390_amd/csrc/k_mfree.hip", "paper_2505_13390_amd/csr
               "paper_2505_13390_amd/csrc/rowops.hpp")
 
 
-def cpu_baseline(w, seconds_hint: float = 20.0):
+def cpu_baseline(w, lmax_scale: float):
     """The FP64 oracle on the same workload: frame 0, global iteration 0,
     a fixed number of preconditioned CG iterations (setup not timed)."""
     import numpy as np
 
     from oracle import oracle as O
-    sim = O.Sim(w)
+    oo = O.default_opts(lmax_scale=lmax_scale)
+    sim = O.Sim(w, oo)
     pos, vel = O.positions(w)
     # semi-implicit Euler predict of frame 0 (what the first global iteration sees)
     free = w.inv_mass > 0
@@ -88,7 +95,7 @@ def cpu_baseline(w, seconds_hint: float = 20.0):
     pos[free] += w.dt * vel[free]
     val, b = sim.assemble(pos)
     rp, col = sim.pattern()
-    h = O.Hier.build(rp, col, val)
+    h = O.Hier.build(rp, col, val, oo)
     iters = 50   # about 10-15 s of single-core work on the 32x32x128 beam
     t0 = time.perf_counter()
     _, st = h.pcg(b, 1e-6, 1000, force_iters=iters)
@@ -162,8 +169,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3"],
-                    help="C3: the 64-beam batch (a comparison run, not the headline line)")
+    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3", "A0", "A1"],
+                    help="C3: the 64-beam batch; A0/A1: the ARAP beams (comparison runs, "
+                         "not the headline line)")
+    ap.add_argument("--lmax-scale", type=float, default=None,
+                    help="margin on the power-method lambda_max (default 1.05; 1.5 for the "
+                         "ARAP beams, whose matrix drifts further between lazy setups)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, mixed for C3")
     ap.add_argument("--sequential", action="store_true",
@@ -203,7 +214,10 @@ def main():
     w = W.CONFIGS[args.config]()
     n_iters = args.iters or w.iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
+    if args.lmax_scale is None:
+        args.lmax_scale = 1.5 if args.config.startswith("A") else 1.05
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
+                                  lmax_scale=args.lmax_scale,
                                   profile_spmv=0 if args.no_profile else 1,
                                   matrix_free=1 if args.fine == "mf" else 0,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
@@ -241,7 +255,8 @@ def main():
         traffic = None
         if args.fine == "mf":
             ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
-            gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol, ne, nvol)
+            nar = int(w.arap_tet.shape[0])
+            gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol + 4 * nar, ne, nvol, nar)
             nbytes = gb + rb
             kname = ("fine-level A p, matrix-free: k_mf_gather + k_mf_rows<OpPcgDot> "
                      "(one launch each)")
@@ -273,6 +288,7 @@ def main():
                    "iters_per_frame": n_iters, "precision": args.precision,
                    "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
                    "smoother": args.smoother, "reuse_interval": args.reuse, "tol": 1e-6,
+                   "lmax_scale": args.lmax_scale,
                    "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
                    "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps},
@@ -289,7 +305,7 @@ def main():
         del src, dst
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, args.lmax_scale)
         print("cpu baseline took %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

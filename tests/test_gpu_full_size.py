@@ -1,7 +1,8 @@
 """Parity at full size, in the configurations bench.py times: the first
 global iteration of frame 0 of the 32x32x128 beam (1,731,776 rows,
 155,246,662 entries; FP64 and FP32 V-cycle) and of the 64-beam batch
-(12,619,205 rows). Checked element by element where the oracle can compute
+(12,619,205 rows), and of the 32x32x128 ARAP beam (786,432 tet rows).
+Checked element by element where the oracle can compute
 the whole result (assembly of A and b, the complete AMG hierarchy of that A,
 the smallest bodies of the batch), and by properties that hold at any size
 elsewhere (true residual of the PCG solve, agreement of the matrix-free and
@@ -169,3 +170,68 @@ def test_c3_batch_full_size():
         log("  body %d (%d rows): position error vs FP64 oracle %.3e" % (k, ws[k].n_rows, err))
         assert err <= 1e-7
     batch.close()
+
+
+def test_a1_arap_full_size():
+    """The 32x32x128 ARAP beam squashed by 30% (786,432 rows) as bench.py runs
+    it: the first global iteration's A and b bit-identical to the oracle's,
+    every level of the hierarchy bit-identical to the oracle's setup on that
+    A, the solve's true residual at the tolerance, and the assembled fine
+    operator agreeing with the matrix-free one. (Solves on this squash are
+    ill-conditioned as inputs to the positions: two solves that both reach
+    1e-6 may leave positions 1e-8 apart, so that comparison uses 1e-7.)"""
+    import scipy.sparse as sp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = W.arap_a1()
+    oo, go = opts(lmax_scale=1.5)
+    body = B.Body(w, go)
+    res = body.step(1)
+    log("A1 GPU first iteration: pcg iters", res["pcg_iters"].tolist(),
+        "ratio %.3e" % res["pcg_ratio"][0])
+    sim = O.Sim(w, oo)
+    val, b = sim.assemble(predicted(w))
+    rp, col = sim.pattern()
+    grp, gcol, gval = B.mgpbd_get_matrix(body.ctx, 0)
+    assert np.array_equal(grp, rp) and np.array_equal(gcol, col)
+    nbad = int((gval.view(np.uint64) != val.view(np.uint64)).sum())
+    gb = B.mgpbd_get_rhs(body.ctx, sim.m)
+    bbad = int((gb.view(np.uint64) != b.view(np.uint64)).sum())
+    log("A1 assembly: %d of %d values, %d of %d rhs entries differ" % (nbad, val.size, bbad,
+                                                                       b.size))
+    assert nbad == 0 and bbad == 0
+    del sim
+    h = O.Hier.build(grp, gcol, gval, oo)
+    L = B.mgpbd_num_levels(body.ctx)
+    log("A1 levels: oracle %d gpu %d" % (h.levels, L))
+    assert L == h.levels
+    for l in range(L):
+        gi = B.mgpbd_get_level(body.ctx, l)
+        log("  level %d: n %d nnz %d" % (l, gi["n"], gi["nnz"]))
+        if l > 0:
+            r, c, v = B.mgpbd_get_matrix(body.ctx, l)
+            orp, ocol, oval = h.matrix(l)
+            assert np.array_equal(r, orp) and np.array_equal(c, ocol)
+            assert np.array_equal(v.view(np.uint64), oval.view(np.uint64)), "level %d" % l
+        if l + 1 < L:
+            oagg, op, oB = h.transfer(l)
+            assert np.array_equal(B.mgpbd_get_aggregates(body.ctx, l), oagg)
+            gp, gB = B.mgpbd_get_transfer(body.ctx, l)
+            assert np.array_equal(gp.view(np.uint64), op.view(np.uint64))
+            assert np.array_equal(gB.view(np.uint64), oB.view(np.uint64))
+    del h
+    A = sp.csr_matrix((gval, gcol, grp))
+    x = B.mgpbd_get_lambda(body.ctx, grp.size - 1)
+    rel = float(np.linalg.norm(A @ x - gb) / np.linalg.norm(gb))
+    log("A1 true relative residual %.3e" % rel)
+    assert res["pcg_ratio"][0] <= 1e-6 and rel <= 1.5e-6
+    _, gcsr = opts(lmax_scale=1.5, matrix_free=0)
+    csr = B.Body(w, gcsr)
+    rc = csr.step(1)
+    err = rel_pos_err(body.positions(), csr.positions())
+    log("A1 matrix-free vs CSR: iters %d / %d, position difference %.3e"
+        % (res["pcg_iters"][0], rc["pcg_iters"][0], err))
+    csr.close()
+    body.close()
+    assert abs(int(res["pcg_iters"][0]) - int(rc["pcg_iters"][0])) <= 0.05 * rc["pcg_iters"][0]
+    assert err <= 1e-7
