@@ -232,6 +232,15 @@ mgpbd_status mgpbd_get_transfer(const mgpbd_ctx *ctx, int32_t l, double *p, doub
 /* sorted CSR of level l: host rowptr [n+1], col [nnz], val [nnz]; any may be NULL */
 mgpbd_status mgpbd_get_matrix(const mgpbd_ctx *ctx, int32_t l, int64_t *rowptr, int32_t *col,
                               double *val);
+/* y = A x with the constraint-space matrix of the last global iteration
+   (Eq. 3), applied the way the PCG loop applies it: matrix-free from the
+   constraint gradients (the future-work direction of the Conclusion and
+   Limitations section) when
+   options.matrix_free is set, else from the assembled CSR. x, y: device FP64
+   [m] (for a batch context, all bodies' rows back to back), not aliased;
+   enqueued on the context's stream (no synchronisation). Errors: E_STATE
+   before the first step. */
+mgpbd_status mgpbd_apply(mgpbd_ctx *ctx, const double *x, double *y);
 /* right-hand side b of the last global iteration, host FP64 [m] */
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *ctx, double *b);
 /* Lagrange multipliers lambda of the current frame, host FP64 [m] */

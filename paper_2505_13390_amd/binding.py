@@ -89,6 +89,7 @@ _SIGS = {
     "mgpbd_get_aggregates": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mgpbd_get_transfer": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mgpbd_get_matrix": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mgpbd_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mgpbd_get_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_lambda": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -297,6 +298,13 @@ def mgpbd_get_matrix(ctx, l):
     val = np.zeros(info["nnz"])
     _check(ctx, lib().mgpbd_get_matrix(ctx, l, _np_ptr(rp), _np_ptr(col), _np_ptr(val)))
     return rp, col, val
+
+
+def mgpbd_apply(ctx, x, y):
+    """y = A x (device FP64 tensors of the context's row count), enqueued on
+    the context's stream."""
+    assert x.dtype == y.dtype and x.is_cuda and y.is_cuda and x.numel() == y.numel()
+    _check(ctx, lib().mgpbd_apply(ctx, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
 
 
 def mgpbd_get_rhs(ctx, m):

@@ -619,6 +619,15 @@ mgpbd_status mgpbd_get_matrix(const mgpbd_ctx *c, int32_t l, int64_t *rowptr, in
   });
 }
 
+mgpbd_status mgpbd_apply(mgpbd_ctx *c, const double *x, double *y) {
+  if (!c || !x || !y || x == y) return MGPBD_E_INVALID_ARG;
+  if (!c->has_body || !c->have_rhs) {
+    c->err = "no assembled system: run a step first";
+    return MGPBD_E_STATE;
+  }
+  return guard(c, [&] { c->solver->apply_fine(x, y); });
+}
+
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *c, double *b) {
   if (!c || !b) return MGPBD_E_INVALID_ARG;
   if (!c->has_body || !c->have_rhs) return MGPBD_E_STATE;

@@ -868,6 +868,18 @@ void Solver::iterate_once(int k) {
   launch_s_pcg_pupdate(t, ctl.p, z.p, p.p, st);
 }
 
+void Solver::apply_fine(const double *x, double *y) {
+  Level &F = *lev[0];
+  MG_REQUIRE(F.n > 0 && F.val.p, MGPBD_E_STATE, "no assembled matrix");
+  ensure_partials(F.tab.view().nblk);
+  if (mf.ok()) {
+    launch_mf_gather(mf, x, nullptr, st);
+    launch_mf_rows_dot(mf, x, y, nullptr, partials(), st);
+  } else {
+    launch_spmv_dot_partials(F.view(), x, y, nullptr, partials(), st);
+  }
+}
+
 std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
                                    const int32_t *force) {
   MG_REQUIRE(built, MGPBD_E_STATE, "solve without a hierarchy");

@@ -132,6 +132,8 @@ class Solver {
   void refresh();
   // MGPCG on A_0 for every body at once: x_out <- A_0^-1 b; force (nullable,
   // [nb]) fixes iteration counts. One result per body.
+  // y = A x on the fine level with the PCG loop's own kernels (no sync)
+  void apply_fine(const double *x, double *y);
   std::vector<PcgResult> pcg(const double *b, double *x_out, double tol, int max_iters,
                              const int32_t *force);
   double *dl() { return x.p; }   // internal PCG iterate

@@ -345,3 +345,34 @@ def test_other_smoothers_mixed_and_batched(smoother):
             assert (res[k]["pcg_ratio"] <= 1e-6).all()
             assert err <= bound
         batch.close()
+
+
+@pytest.mark.parametrize("mf,arap", [(1, False), (0, False), (1, True)])
+def test_apply_entry_matches_assembled_matrix(mf, arap):
+    """mgpbd_apply (the PCG loop's own fine-level product) against the
+    assembled A of the same iteration, multiplied on the host: equal up to
+    the order of the sums (1e-13 of |A| |x| per row)."""
+    import scipy.sparse as sp
+    w = W.arap_beam(12, 4, 4, seed=61, squash=0.1) if arap else W.beam_c0()
+    _, go = opts(matrix_free=mf, lmax_scale=1.5 if arap else 1.05)
+    body = B.Body(w, go)
+    body.step(1)
+    rp, col, val = B.mgpbd_get_matrix(body.ctx, 0)
+    A = sp.csr_matrix((val, col, rp))
+    m = rp.size - 1
+    x = np.random.default_rng(3).standard_normal(m)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    yt = torch.empty_like(xt)
+    B.mgpbd_apply(body.ctx, xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    ref = A @ x
+    scale = abs(A) @ np.abs(x)
+    err = float((np.abs(y - ref) / scale).max())
+    log("apply (matrix_free=%d, arap=%s): max row error %.3e of |A||x|" % (mf, arap, err))
+    body.close()
+    assert err <= 1e-13
+    solver = B.mgpbd_solver_create(go)   # no assembled system: E_STATE
+    with pytest.raises(B.MgpbdError):
+        B.mgpbd_apply(solver, xt, yt)
+    B.mgpbd_destroy(solver)
