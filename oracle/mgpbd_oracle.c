@@ -45,8 +45,12 @@
  *    (arap_eval, with the readings listed there).
  *
  * Readings where the paper is silent (each listed in the design notes):
- *  - one near-kernel candidate per aggregate (K = 1): P column = candidate
- *    restricted to the aggregate and normalised; next-level candidate = norm;
+ *  - by default one near-kernel candidate per aggregate (K = 1): P column =
+ *    candidate restricted to the aggregate and normalised; next-level
+ *    candidate = norm. Option n_cand = K > 1 (Sec. 4.3 generates six):
+ *    K candidates from K random starts, modified Gram-Schmidt QR per
+ *    aggregate with dependent columns dropped (qr_aggregate), so an
+ *    aggregate gives 1..K coarse unknowns;
  *  - aggregation pass 1 is the greedy distance-2 independent set taken in
  *    descending pseudo-random priority; pass 2 joins the neighbour with the
  *    largest |a_ij| (ties: smallest j); aggregates numbered by root index;
@@ -89,6 +93,7 @@ typedef struct orc_opts {
   int flexible;        /* 0 = Fletcher-Reeves beta, 1 = Polak-Ribiere beta */
   double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 */
   int smoother;        /* 0 = omega-Jacobi, 1 = Chebyshev, 2 = multicolour GS (Sec. 4.5): 0 */
+  int n_cand;          /* near-kernel candidates per level K (Sec. 4.3 uses six): 1 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -111,6 +116,7 @@ void orc_default_opts(orc_opts *o) {
   o->flexible = 0;
   o->lmax_scale = 1.05;
   o->smoother = 0;
+  o->n_cand = 1;
 }
 
 /* ------------------------------------------------------------------ */
@@ -703,8 +709,14 @@ typedef struct {
   int64_t n_agg;
   int64_t *agg_ptr;   /* members of each aggregate, ascending */
   int32_t *agg_mem;
-  double *p;          /* P value of each row (0 for isolated rows) */
-  double *B;          /* near-kernel candidate on this level */
+  /* P: the columns of aggregate q are the coarse unknowns coff[q] ..
+     coff[q] + kq[q] - 1; member slot m (position in agg_mem) holds its row
+     of P in Q[m K .. m K + kq - 1] (zeros beyond kq); slot[i] = slot of row i */
+  int32_t *kq;
+  int64_t *coff;
+  int32_t *slot;
+  double *Q;
+  double *B;          /* near-kernel candidates on this level, [n][K] */
   int32_t *color;     /* level 0: multicolour GS order */
   int n_colors;
   /* Gauss-Seidel smoother: rows grouped by colour */
@@ -727,7 +739,8 @@ typedef struct {
 static void level_free(level_t *lv) {
   csr_free(&lv->A);
   free(lv->diag); free(lv->agg); free(lv->agg_ptr); free(lv->agg_mem);
-  free(lv->p); free(lv->B); free(lv->color); free(lv->sm_ptr); free(lv->sm_rows);
+  free(lv->kq); free(lv->coff); free(lv->slot); free(lv->Q);
+  free(lv->B); free(lv->color); free(lv->sm_ptr); free(lv->sm_rows);
   memset(lv, 0, sizeof *lv);
 }
 
@@ -871,18 +884,24 @@ static void gs_sweep_homog(const csr *a, const double *diag, const int32_t *colo
     }
 }
 
-/* Galerkin product A_c = P^T A P (Eq. 6) with P one value per row:
-   entry (a, b), a <= b, = sum over fine entries (i, j) with agg(i) = a,
-   agg(j) = b, taken in ascending i then ascending j, of (p_i a_ij) p_j;
-   entry (b, a) is the same number (A_c is symmetric). */
-static int galerkin_pattern(const csr *a, const int32_t *agg, int64_t na, csr *c) {
-  c->n = na;
-  c->rowptr = calloc(na + 1, sizeof(int64_t));
+/* Galerkin product A_c = P^T A P (Eq. 6). Coarse unknowns are the
+   (aggregate, column) pairs (a, s), numbered coff[a] + s. The pattern of
+   A_c: row (a, s) holds (b, t) for every aggregate b that some fine entry
+   (i, j), agg(i) = a, agg(j) = b, reaches, and every t < kq[b]; columns
+   ascending. Entry ((a, s), (b, t)) above or on the diagonal = sum over those
+   fine entries, taken in ascending i then ascending j, of
+   (Q_i,s a_ij) Q_j,t; an entry below the diagonal takes the value of its
+   mirror above it (A_c is symmetric). With one candidate this is the sum
+   of (p_i a_ij) p_j. */
+static int galerkin_pattern(const csr *a, const int32_t *agg, int64_t na, const int32_t *kq,
+                            const int64_t *coff, csr *c) {
+  /* aggregate-level pattern first */
+  int64_t *arp = calloc(na + 1, sizeof(int64_t));
   int32_t *mark = malloc(sizeof(int32_t) * (na ? na : 1));
-  if (!c->rowptr || !mark) return ORC_E_NOMEM;
+  int64_t *mptr = calloc(na + 1, sizeof(int64_t));
+  if (!arp || !mark || !mptr) { free(arp); free(mark); free(mptr); return ORC_E_NOMEM; }
   for (int64_t q = 0; q < na; ++q) mark[q] = -1;
   /* members of each aggregate, ascending: count then fill */
-  int64_t *mptr = calloc(na + 1, sizeof(int64_t));
   for (int64_t i = 0; i < a->n; ++i) if (agg[i] >= 0) mptr[agg[i] + 1]++;
   for (int64_t q = 0; q < na; ++q) mptr[q + 1] += mptr[q];
   int32_t *mem = malloc(sizeof(int32_t) * (mptr[na] ? mptr[na] : 1));
@@ -898,25 +917,42 @@ static int galerkin_pattern(const csr *a, const int32_t *agg, int64_t na, csr *c
         if (b >= 0 && mark[b] != (int32_t)q) { mark[b] = (int32_t)q; cnt++; }
       }
     }
-    c->rowptr[q + 1] = c->rowptr[q] + cnt;
+    arp[q + 1] = arp[q] + cnt;
   }
-  c->nnz = c->rowptr[na];
-  c->col = malloc(sizeof(int32_t) * (c->nnz ? c->nnz : 1));
-  c->val = calloc(c->nnz ? c->nnz : 1, sizeof(double));
+  int32_t *acol = malloc(sizeof(int32_t) * (arp[na] ? arp[na] : 1));
   for (int64_t q = 0; q < na; ++q) mark[q] = -1;
   for (int64_t q = 0; q < na; ++q) {
-    int64_t k = c->rowptr[q];
+    int64_t k = arp[q];
     for (int64_t t = mptr[q]; t < mptr[q + 1]; ++t) {
       int32_t i = mem[t];
       for (int64_t e = a->rowptr[i]; e < a->rowptr[i + 1]; ++e) {
         int32_t b = agg[a->col[e]];
-        if (b >= 0 && mark[b] != (int32_t)q) { mark[b] = (int32_t)q; c->col[k++] = b; }
+        if (b >= 0 && mark[b] != (int32_t)q) { mark[b] = (int32_t)q; acol[k++] = b; }
       }
     }
-    qsort(c->col + c->rowptr[q], (size_t)(c->rowptr[q + 1] - c->rowptr[q]), sizeof(int32_t),
-          cmp_i32);
+    qsort(acol + arp[q], (size_t)(arp[q + 1] - arp[q]), sizeof(int32_t), cmp_i32);
   }
-  free(mark); free(mptr); free(mem); free(cur);
+  /* expand every aggregate entry (a, b) into the block of (a, s) x (b, t) */
+  int64_t nc = coff[na];
+  c->n = nc;
+  c->rowptr = calloc(nc + 1, sizeof(int64_t));
+  if (!c->rowptr) { free(arp); free(mark); free(mptr); free(mem); free(cur); free(acol); return ORC_E_NOMEM; }
+  for (int64_t q = 0; q < na; ++q) {
+    int64_t len = 0;
+    for (int64_t e = arp[q]; e < arp[q + 1]; ++e) len += kq[acol[e]];
+    for (int s = 0; s < kq[q]; ++s) c->rowptr[coff[q] + s + 1] = len;
+  }
+  for (int64_t r = 0; r < nc; ++r) c->rowptr[r + 1] += c->rowptr[r];
+  c->nnz = c->rowptr[nc];
+  c->col = malloc(sizeof(int32_t) * (c->nnz ? c->nnz : 1));
+  c->val = calloc(c->nnz ? c->nnz : 1, sizeof(double));
+  for (int64_t q = 0; q < na; ++q)
+    for (int s = 0; s < kq[q]; ++s) {
+      int64_t k = c->rowptr[coff[q] + s];
+      for (int64_t e = arp[q]; e < arp[q + 1]; ++e)
+        for (int t = 0; t < kq[acol[e]]; ++t) c->col[k++] = (int32_t)(coff[acol[e]] + t);
+    }
+  free(arp); free(mark); free(mptr); free(mem); free(cur); free(acol);
   return ORC_OK;
 }
 
@@ -930,17 +966,24 @@ static int64_t find_col(const csr *c, int64_t row, int32_t colv) {
   return -1;
 }
 
-static void galerkin_values(const csr *a, const int32_t *agg, const double *p, csr *c) {
+static void galerkin_values(const csr *a, const level_t *lv, int K, csr *c) {
   for (int64_t k = 0; k < c->nnz; ++k) c->val[k] = 0.0;
   for (int64_t i = 0; i < a->n; ++i) {
-    int32_t ai = agg[i];
+    int32_t ai = lv->agg[i];
     if (ai < 0) continue;
+    const double *qi = lv->Q + (int64_t)lv->slot[i] * K;
     for (int64_t e = a->rowptr[i]; e < a->rowptr[i + 1]; ++e) {
       int32_t j = a->col[e];
-      int32_t bj = agg[j];
+      int32_t bj = lv->agg[j];
       if (bj < 0) continue;
-      int64_t k = find_col(c, ai, bj);
-      c->val[k] = c->val[k] + (p[i] * a->val[e]) * p[j];
+      const double *qj = lv->Q + (int64_t)lv->slot[j] * K;
+      for (int s = 0; s < lv->kq[ai]; ++s) {
+        int64_t r = lv->coff[ai] + s;
+        for (int t = 0; t < lv->kq[bj]; ++t) {
+          int64_t k = find_col(c, r, (int32_t)(lv->coff[bj] + t));
+          c->val[k] = c->val[k] + (qi[s] * a->val[e]) * qj[t];
+        }
+      }
     }
   }
   /* keep the coarse matrix exactly symmetric: the entry below the diagonal
@@ -1066,13 +1109,61 @@ static int finish_level(hier_t *h, int l) {
   return ORC_OK;
 }
 
+/* QR of the K candidates restricted to one aggregate (its s rows, ascending)
+   by modified Gram-Schmidt (Golub and Van Loan, Sec. 5.2.8): column k has
+   its projections on the columns kept so far removed one after another, and
+   is kept (normalised) unless what remains is at most ORC_QR_DROP of its
+   norm, i.e. it is numerically dependent on the kept ones (always the case
+   past s columns). Q [s][K] gets the kept columns (zeros beyond them), R
+   [K][K] row j the coefficients of kept column j (R = Q^T B). A zero block
+   keeps one normalised all-ones column with R[0][0] = sqrt(s). Returns the
+   number of kept columns. With K = 1: Q = b / |b|, R = |b|. */
+#define ORC_QR_DROP 1e-8
+static int qr_aggregate(const double *B, int K, const int32_t *mem, int64_t s, double *Q,
+                        double *R) {
+  double *v = malloc(sizeof(double) * (s ? s : 1));
+  int kept = 0;
+  for (int k = 0; k < K; ++k) {
+    double n0 = 0.0;
+    for (int64_t t = 0; t < s; ++t) {
+      v[t] = B[(int64_t)mem[t] * K + k];
+      n0 = n0 + v[t] * v[t];
+    }
+    n0 = sqrt(n0);
+    for (int j = 0; j < kept; ++j) {
+      double r = 0.0;
+      for (int64_t t = 0; t < s; ++t) r = r + Q[t * K + j] * v[t];
+      R[j * K + k] = r;
+      for (int64_t t = 0; t < s; ++t) v[t] = v[t] - r * Q[t * K + j];
+    }
+    double nr = 0.0;
+    for (int64_t t = 0; t < s; ++t) nr = nr + v[t] * v[t];
+    nr = sqrt(nr);
+    if (nr > 0.0 && nr > ORC_QR_DROP * n0) {
+      for (int64_t t = 0; t < s; ++t) Q[t * K + kept] = v[t] / nr;
+      R[kept * K + k] = nr;
+      ++kept;
+    }
+  }
+  if (kept == 0) {
+    double sa = sqrt((double)s);
+    for (int64_t t = 0; t < s; ++t) Q[t * K] = 1.0 / sa;
+    R[0] = sa;
+    kept = 1;
+  }
+  free(v);
+  return kept;
+}
+
 hier_t *orc_hier_build(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                        const orc_opts *opts, int *status) {
   hier_t *h = calloc(1, sizeof *h);
   if (!h) { *status = ORC_E_NOMEM; return NULL; }
   if (opts) h->o = *opts; else orc_default_opts(&h->o);
   const orc_opts *o = &h->o;
-  if (o->max_levels < 1 || o->max_levels > 32) { *status = ORC_E_INVALID; free(h); return NULL; }
+  if (o->max_levels < 1 || o->max_levels > 32 || o->n_cand < 1 || o->n_cand > 8) {
+    *status = ORC_E_INVALID; free(h); return NULL;
+  }
   for (int64_t i = 0; i < n; ++i)
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
       if (col[e] < 0 || col[e] >= n || (e > rowptr[i] && col[e] <= col[e - 1])) {
@@ -1100,15 +1191,15 @@ hier_t *orc_hier_build(int64_t n, const int64_t *rowptr, const int32_t *col, con
     if (na == 0) break; /* every row isolated: nothing to coarsen */
     /* candidate on this level: level 0 from Gauss-Seidel sweeps on A x = 0
        (Sec. 4.3) or all ones; deeper levels inherit the norms from above */
+    const int K = o->n_cand;
     if (l == 0) {
-      lv->B = malloc(sizeof(double) * nl);
+      lv->B = malloc(sizeof(double) * nl * K);
       if (o->b_mode == 1) {
-        for (int64_t i = 0; i < nl; ++i) lv->B[i] = 1.0;
+        for (int64_t i = 0; i < nl * K; ++i) lv->B[i] = 1.0;
       } else {
         double amax = 0.0;
         for (int64_t e = 0; e < lv->A.nnz; ++e)
           if (fabs(lv->A.val[e]) > amax) amax = fabs(lv->A.val[e]);
-        for (int64_t i = 0; i < nl; ++i) lv->B[i] = uniform01(o->seed, 2, (uint64_t)i) * amax;
         uint64_t *cp = malloc(sizeof(uint64_t) * nl);
         for (int64_t i = 0; i < nl; ++i) cp[i] = prio_key(o->seed, 4, 0, i);
         lv->color = malloc(sizeof(int32_t) * nl);
@@ -1121,13 +1212,21 @@ hier_t *orc_hier_build(int64_t n, const int64_t *rowptr, const int32_t *col, con
         int64_t *cc = malloc(sizeof(int64_t) * (lv->n_colors ? lv->n_colors : 1));
         memcpy(cc, cptr, sizeof(int64_t) * lv->n_colors);
         for (int64_t i = 0; i < nl; ++i) crow[cc[lv->color[i]]++] = (int32_t)i;
-        for (int s = 0; s < o->gs_sweeps; ++s)
-          gs_sweep_homog(&lv->A, lv->diag, lv->color, lv->n_colors, cptr, crow, lv->B);
-        free(cptr); free(crow); free(cc);
+        /* candidate k: its own random start (index k 2^40 + i of stream 2),
+           then the same sweeps */
+        double *x = malloc(sizeof(double) * nl);
+        for (int k = 0; k < K; ++k) {
+          for (int64_t i = 0; i < nl; ++i)
+            x[i] = uniform01(o->seed, 2, ((uint64_t)k << 40) + (uint64_t)i) * amax;
+          for (int s = 0; s < o->gs_sweeps; ++s)
+            gs_sweep_homog(&lv->A, lv->diag, lv->color, lv->n_colors, cptr, crow, x);
+          for (int64_t i = 0; i < nl; ++i) lv->B[i * K + k] = x[i];
+        }
+        free(x); free(cptr); free(crow); free(cc);
       }
     }
-    /* injection: P value = candidate / its norm on the aggregate (one-column
-       QR: Q -> P, R -> next-level candidate); zero norm -> all-ones column */
+    /* injection: QR of the candidates restricted to each aggregate (Sec. 4.1):
+       Q -> the aggregate's columns of P, R -> the next level's candidates */
     lv->agg_ptr = calloc(na + 1, sizeof(int64_t));
     lv->agg_mem = malloc(sizeof(int32_t) * (nl ? nl : 1));
     for (int64_t i = 0; i < nl; ++i) if (lv->agg[i] >= 0) lv->agg_ptr[lv->agg[i] + 1]++;
@@ -1139,31 +1238,33 @@ hier_t *orc_hier_build(int64_t n, const int64_t *rowptr, const int32_t *col, con
         if (lv->agg[i] >= 0) lv->agg_mem[cur[lv->agg[i]]++] = (int32_t)i;
       free(cur);
     }
-    lv->p = calloc(nl ? nl : 1, sizeof(double));
-    double *Bn = malloc(sizeof(double) * na);
+    int64_t nmem = lv->agg_ptr[na];
+    lv->slot = malloc(sizeof(int32_t) * (nl ? nl : 1));
+    for (int64_t i = 0; i < nl; ++i) lv->slot[i] = -1;
+    for (int64_t m = 0; m < nmem; ++m) lv->slot[lv->agg_mem[m]] = (int32_t)m;
+    lv->Q = calloc((size_t)(nmem ? nmem : 1) * K, sizeof(double));
+    lv->kq = calloc(na ? na : 1, sizeof(int32_t));
+    lv->coff = calloc(na + 1, sizeof(int64_t));
+    double *R = calloc((size_t)(na ? na : 1) * K * K, sizeof(double));
     for (int64_t q = 0; q < na; ++q) {
-      double s = 0.0;
-      for (int64_t t = lv->agg_ptr[q]; t < lv->agg_ptr[q + 1]; ++t) {
-        double bi = lv->B[lv->agg_mem[t]];
-        s = s + bi * bi;
-      }
-      double sa = sqrt(s);
-      if (sa == 0.0) {
-        sa = sqrt((double)(lv->agg_ptr[q + 1] - lv->agg_ptr[q]));
-        for (int64_t t = lv->agg_ptr[q]; t < lv->agg_ptr[q + 1]; ++t)
-          lv->p[lv->agg_mem[t]] = 1.0 / sa;
-      } else {
-        for (int64_t t = lv->agg_ptr[q]; t < lv->agg_ptr[q + 1]; ++t)
-          lv->p[lv->agg_mem[t]] = lv->B[lv->agg_mem[t]] / sa;
-      }
-      Bn[q] = sa;
+      int kept = qr_aggregate(lv->B, K, lv->agg_mem + lv->agg_ptr[q],
+                              lv->agg_ptr[q + 1] - lv->agg_ptr[q],
+                              lv->Q + lv->agg_ptr[q] * K, R + q * K * K);
+      lv->kq[q] = kept;
+      lv->coff[q + 1] = lv->coff[q] + kept;
     }
+    int64_t nnext = lv->coff[na];
+    double *Bn = malloc(sizeof(double) * (nnext ? nnext : 1) * K);
+    for (int64_t q = 0; q < na; ++q)
+      for (int j = 0; j < lv->kq[q]; ++j)
+        for (int k = 0; k < K; ++k) Bn[(lv->coff[q] + j) * K + k] = R[(q * K + j) * K + k];
+    free(R);
     level_t *nx = &h->lev[l + 1];
-    *status = galerkin_pattern(&lv->A, lv->agg, na, &nx->A);
+    *status = galerkin_pattern(&lv->A, lv->agg, na, lv->kq, lv->coff, &nx->A);
     if (*status != ORC_OK) { free(Bn); orc_hier_free(h); return NULL; }
-    galerkin_values(&lv->A, lv->agg, lv->p, &nx->A);
+    galerkin_values(&lv->A, lv, K, &nx->A);
     nx->B = Bn;
-    if ((double)na > 0.95 * (double)nl) force_last = stalled = 1; /* coarsening stalled */
+    if ((double)nnext > 0.95 * (double)nl) force_last = stalled = 1; /* coarsening stalled */
   }
   level_t *last = &h->lev[h->L - 1];
   if (last->A.n <= o->dense_max) {
@@ -1188,7 +1289,7 @@ int orc_hier_refresh(hier_t *h, const double *val0) {
   for (int l = 0; l < h->L; ++l) {
     level_t *lv = &h->lev[l];
     for (int64_t i = 0; i < lv->A.n; ++i) lv->diag[i] = csr_get_diag(&lv->A, i);
-    if (l + 1 < h->L) galerkin_values(&lv->A, lv->agg, lv->p, &h->lev[l + 1].A);
+    if (l + 1 < h->L) galerkin_values(&lv->A, lv, h->o.n_cand, &h->lev[l + 1].A);
   }
   for (int l = 0; l < h->L; ++l)
     for (int64_t i = 0; i < h->lev[l].A.n; ++i)
@@ -1283,18 +1384,27 @@ static void vcycle(hier_t *h, int l, const double *r, double *z) {
     spmv(&lv->A, z, t);
     for (int64_t i = 0; i < n; ++i) res[i] = r[i] - t[i];
     int64_t na = lv->n_agg;
+    const int K = h->o.n_cand;
     double *rc = h->rc[l + 1], *zc = h->zc[l + 1];
-    for (int64_t q = 0; q < na; ++q) {
-      double s = 0.0;
-      for (int64_t k = lv->agg_ptr[q]; k < lv->agg_ptr[q + 1]; ++k) {
-        int32_t i = lv->agg_mem[k];
-        s = s + lv->p[i] * res[i];
+    /* restriction P^T res: coarse unknown (q, s) sums Q_i,s res_i over the
+       aggregate's rows in ascending order */
+    for (int64_t q = 0; q < na; ++q)
+      for (int s = 0; s < lv->kq[q]; ++s) {
+        double acc = 0.0;
+        for (int64_t m = lv->agg_ptr[q]; m < lv->agg_ptr[q + 1]; ++m)
+          acc = acc + lv->Q[m * K + s] * res[lv->agg_mem[m]];
+        rc[lv->coff[q] + s] = acc;
       }
-      rc[q] = s;
-    }
     vcycle(h, l + 1, rc, zc);
-    for (int64_t i = 0; i < n; ++i)
-      if (lv->agg[i] >= 0) z[i] = z[i] + lv->p[i] * zc[lv->agg[i]];
+    /* prolongation z += P zc */
+    for (int64_t i = 0; i < n; ++i) {
+      int32_t q = lv->agg[i];
+      if (q < 0) continue;
+      const double *qi = lv->Q + (int64_t)lv->slot[i] * K;
+      double acc = 0.0;
+      for (int s = 0; s < lv->kq[q]; ++s) acc = acc + qi[s] * zc[lv->coff[q] + s];
+      z[i] = z[i] + acc;
+    }
   }
   if (gs) {
     gs_smooth(h, l, r, z, h->o.post_sweeps, 1);
@@ -1328,13 +1438,30 @@ void orc_hier_level_matrix(const hier_t *h, int l, int64_t *rowptr, int32_t *col
   if (val) memcpy(val, lv->A.val, sizeof(double) * lv->A.nnz);
 }
 
-/* agg / p / candidate of level l (only for levels that have a coarser one) */
+/* agg, P's first column (one value per row, 0 for isolated rows) and the
+   first candidate of level l (only for levels that have a coarser one) */
 int orc_hier_level_transfer(const hier_t *h, int l, int32_t *agg, double *p, double *B) {
   const level_t *lv = &h->lev[l];
+  const int K = h->o.n_cand;
   if (!lv->agg) return ORC_E_INVALID;
   if (agg) memcpy(agg, lv->agg, sizeof(int32_t) * lv->A.n);
-  if (p) memcpy(p, lv->p, sizeof(double) * lv->A.n);
-  if (B) memcpy(B, lv->B, sizeof(double) * lv->A.n);
+  for (int64_t i = 0; i < lv->A.n; ++i) {
+    if (p) p[i] = lv->slot[i] >= 0 ? lv->Q[(int64_t)lv->slot[i] * K] : 0.0;
+    if (B) B[i] = lv->B[i * K];
+  }
+  return ORC_OK;
+}
+
+/* the full transfer of level l: kq [n_agg], coff [n_agg + 1], Q [members][K]
+   (member order of the ascending aggregate lists), candidates B [n][K] */
+int orc_hier_level_qr(const hier_t *h, int l, int32_t *kq, int64_t *coff, double *Q, double *B) {
+  const level_t *lv = &h->lev[l];
+  const int K = h->o.n_cand;
+  if (!lv->agg) return ORC_E_INVALID;
+  if (kq) memcpy(kq, lv->kq, sizeof(int32_t) * lv->n_agg);
+  if (coff) memcpy(coff, lv->coff, sizeof(int64_t) * (lv->n_agg + 1));
+  if (Q) memcpy(Q, lv->Q, sizeof(double) * lv->agg_ptr[lv->n_agg] * K);
+  if (B) memcpy(B, lv->B, sizeof(double) * lv->A.n * K);
   return ORC_OK;
 }
 

@@ -34,7 +34,7 @@ class Opts(C.Structure):
                 ("omega_relax", C.c_double), ("tol", C.c_double), ("max_pcg", C.c_int),
                 ("seed", C.c_uint64), ("reuse_interval", C.c_int), ("b_mode", C.c_int),
                 ("eps_b", C.c_double), ("flexible", C.c_int), ("lmax_scale", C.c_double),
-                ("smoother", C.c_int)]
+                ("smoother", C.c_int), ("n_cand", C.c_int)]
 
 
 _lib = None
@@ -90,6 +90,8 @@ def lib():
         L.orc_hier_level_matrix.argtypes = [P, C.c_int, P, P, P]
         L.orc_hier_level_transfer.restype = C.c_int
         L.orc_hier_level_transfer.argtypes = [P, C.c_int, P, P, P]
+        L.orc_hier_level_qr.restype = C.c_int
+        L.orc_hier_level_qr.argtypes = [P, C.c_int, P, P, P, P]
         L.orc_hier_colors.restype = C.c_int
         L.orc_hier_colors.argtypes = [P, P]
         L.orc_pcg.restype = C.c_int
@@ -184,6 +186,21 @@ class Hier:
         if st != OK:
             raise OracleError(st, "transfer")
         return agg, p, B
+
+    def transfer_qr(self, l, K):
+        """kq [n_agg], coff [n_agg + 1], Q [members, K], B [n, K] of level l."""
+        info = self.info(l)
+        n, na = info["n"], info["n_agg"]
+        kq = np.zeros(na, np.int32)
+        coff = np.zeros(na + 1, np.int64)
+        agg, _, _ = self.transfer(l)
+        nmem = int((agg >= 0).sum())
+        Q = np.zeros((nmem, K))
+        B = np.zeros((n, K))
+        st = lib().orc_hier_level_qr(self.h, l, _p(kq), _p(coff), _p(Q), _p(B))
+        if st != OK:
+            raise OracleError(st, "transfer_qr")
+        return kq, coff, Q, B
 
     def colors(self):
         n = self.info(0)["n"]
