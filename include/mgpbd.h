@@ -95,6 +95,12 @@ typedef struct {
                            (greedy colouring of every level at setup; forward colour
                            order before the coarse correction, reversed after; the
                            sweeps read the assembled values): 0 */
+  int32_t n_cand;       /* near-kernel candidates per level K, 1..8 (Sec. 4.3 generates
+                           six): K > 1 factorises each aggregate's K candidates by
+                           modified Gram-Schmidt, dropping columns whose remainder is at
+                           most 1e-8 of their norm, so an aggregate has 1..K coarse
+                           unknowns; P takes the Q blocks and the next level's
+                           candidates the R rows. 1 = one normalised candidate: 1 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.
@@ -241,6 +247,13 @@ mgpbd_status mgpbd_get_matrix(const mgpbd_ctx *ctx, int32_t l, int64_t *rowptr, 
    enqueued on the context's stream (no synchronisation). Errors: E_STATE
    before the first step. */
 mgpbd_status mgpbd_apply(mgpbd_ctx *ctx, const double *x, double *y);
+/* The K > 1 transfer of level l (n_cand > 1 only, E_STATE otherwise): host kq
+   [n_agg] (coarse unknowns of each aggregate), coff [n_agg + 1] (first coarse
+   unknown of each), Q [members][n_cand] (P's row of each aggregate member, in
+   the order of the ascending member lists, zeros past kq), B [n][n_cand] (the
+   level's candidates); any may be NULL. */
+mgpbd_status mgpbd_get_qr(const mgpbd_ctx *ctx, int32_t l, int32_t *kq, int64_t *coff, double *Q,
+                          double *B);
 /* right-hand side b of the last global iteration, host FP64 [m] */
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *ctx, double *b);
 /* Lagrange multipliers lambda of the current frame, host FP64 [m] */

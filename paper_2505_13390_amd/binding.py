@@ -30,7 +30,7 @@ class Options(C.Structure):
                 ("lmax_scale", C.c_double), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("profile_spmv", C.c_int32),
                 ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32),
-                ("matrix_free", C.c_int32), ("smoother", C.c_int32)]
+                ("matrix_free", C.c_int32), ("smoother", C.c_int32), ("n_cand", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -90,6 +90,8 @@ _SIGS = {
     "mgpbd_get_transfer": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mgpbd_get_matrix": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mgpbd_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mgpbd_get_qr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
     "mgpbd_get_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_lambda": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -305,6 +307,16 @@ def mgpbd_apply(ctx, x, y):
     the context's stream."""
     assert x.dtype == y.dtype and x.is_cuda and y.is_cuda and x.numel() == y.numel()
     _check(ctx, lib().mgpbd_apply(ctx, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+
+
+def mgpbd_get_qr(ctx, l, n, n_agg, n_mem, K):
+    """kq [n_agg], coff [n_agg + 1], Q [n_mem, K], B [n, K] of level l (K > 1)."""
+    kq = np.zeros(n_agg, np.int32)
+    coff = np.zeros(n_agg + 1, np.int64)
+    Q = np.zeros((n_mem, K))
+    B = np.zeros((n, K))
+    _check(ctx, lib().mgpbd_get_qr(ctx, l, _np_ptr(kq), _np_ptr(coff), _np_ptr(Q), _np_ptr(B)))
+    return kq, coff, Q, B
 
 
 def mgpbd_get_rhs(ctx, m):

@@ -116,6 +116,7 @@ void check_options(const mgpbd_options &o) {
              "matrix_free must be 0 or 1");
   MG_REQUIRE(o.smoother >= 0 && o.smoother <= 2, MGPBD_E_INVALID_ARG,
              "smoother must be 0 (omega-Jacobi), 1 (Chebyshev) or 2 (Gauss-Seidel)");
+  MG_REQUIRE(o.n_cand >= 1 && o.n_cand <= 8, MGPBD_E_INVALID_ARG, "n_cand must be in 1..8");
 }
 
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
@@ -325,6 +326,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->spmv_lanes = 0;
   o->matrix_free = 1;
   o->smoother = 0;
+  o->n_cand = 1;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {
@@ -594,11 +596,28 @@ mgpbd_status mgpbd_get_aggregates(const mgpbd_ctx *c, int32_t l, int32_t *agg) {
   });
 }
 
+mgpbd_status mgpbd_get_qr(const mgpbd_ctx *c, int32_t l, int32_t *kq, int64_t *coff, double *Q,
+                          double *B) {
+  mgpbd_status s = level_ok(c, l);
+  if (s != MGPBD_OK) return s;
+  const Level &L = *c->solver->lev[l];
+  if (!L.has_next) return MGPBD_E_INVALID_ARG;
+  if (L.K < 2) return MGPBD_E_STATE;
+  return guard(const_cast<mgpbd_ctx *>(c), [&] {
+    if (kq) L.kq.download(kq, L.n_agg, c->st);
+    if (coff) L.coff.download(coff, L.n_agg + 1, c->st);
+    if (Q) L.Q.download(Q, L.nmem * L.K, c->st);
+    if (B) L.B.download(B, L.n * L.K, c->st);
+    MG_HIP(hipStreamSynchronize(c->st));
+  });
+}
+
 mgpbd_status mgpbd_get_transfer(const mgpbd_ctx *c, int32_t l, double *p, double *B) {
   mgpbd_status s = level_ok(c, l);
   if (s != MGPBD_OK) return s;
   const Level &L = *c->solver->lev[l];
   if (!L.has_next) return MGPBD_E_INVALID_ARG;
+  if (L.K > 1) return MGPBD_E_STATE;   // mgpbd_get_qr
   return guard(const_cast<mgpbd_ctx *>(c), [&] {
     if (p) L.p.download(p, L.n, c->st);
     if (B) L.B.download(B, L.n, c->st);

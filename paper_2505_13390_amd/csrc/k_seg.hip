@@ -439,17 +439,18 @@ void launch_s_absmax(const SegTab &t, const int64_t *rp, const double *val,
                      unsigned long long *amax, hipStream_t s) {
   k_s_absmax<<<t.nblk, kBlock, 0, s>>>(t, rp, val, amax);
 }
+// random start of a near-kernel candidate: index idx_off + body-local row
 __global__ void k_s_candidate_init(SegTab t, uint64_t salt, const unsigned long long *amax,
-                                   double *__restrict__ B) {
+                                   uint64_t idx_off, double *__restrict__ B) {
   SEG_BLOCK(t);
   const int64_t base = t.segoff[seg];
   const double am = __longlong_as_double((long long)amax[seg]);
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    B[i] = uniform_open(mix64_salted(salt, (uint64_t)(i - base))) * am;
+    B[i] = uniform_open(mix64_salted(salt, idx_off + (uint64_t)(i - base))) * am;
 }
 void launch_s_candidate_init(const SegTab &t, uint64_t salt, const unsigned long long *amax,
-                             double *B, hipStream_t s) {
-  k_s_candidate_init<<<t.nblk, kBlock, 0, s>>>(t, salt, amax, B);
+                             uint64_t idx_off, double *B, hipStream_t s) {
+  k_s_candidate_init<<<t.nblk, kBlock, 0, s>>>(t, salt, amax, idx_off, B);
 }
 __global__ void k_s_mis_init(SegTab t, const uint8_t *__restrict__ conn, uint64_t salt, int level,
                              uint64_t *__restrict__ key) {

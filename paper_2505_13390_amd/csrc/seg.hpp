@@ -71,7 +71,7 @@ void launch_s_wdinv(const SegTab &t, const double *omega, const double *dinv, do
 void launch_s_absmax(const SegTab &t, const int64_t *rp, const double *val,
                      unsigned long long *amax, hipStream_t s);
 void launch_s_candidate_init(const SegTab &t, uint64_t salt, const unsigned long long *amax,
-                             double *B, hipStream_t s);
+                             uint64_t idx_off, double *B, hipStream_t s);
 // aggregation / colouring keys from body-local row indices
 void launch_s_mis_init(const SegTab &t, const uint8_t *conn, uint64_t salt, int level,
                        uint64_t *key, hipStream_t s);

@@ -64,4 +64,31 @@ void launch_gal_numeric(int64_t nnzc, const int32_t *crow, const int32_t *ccol,
                         const int32_t *gl_row, const int32_t *fcol, const double *fval,
                         const double *p, double *cval, float *cval32, hipStream_t s);
 
+// K > 1 candidates (k_cand.hip)
+void launch_put_column(int64_t n, int K, int k, const double *x, double *B, hipStream_t s);
+void launch_qr_agg(int64_t na, int K, const int64_t *ap, const int32_t *mem, const double *B,
+                   double *Q, double *R, int32_t *kq, hipStream_t s);
+void launch_scatter_r(int64_t na, int K, const int32_t *kq, const int64_t *coff, const double *R,
+                      double *Bn, hipStream_t s);
+void launch_member_slots(int64_t nmem, const int32_t *mem, int32_t *slot, hipStream_t s);
+void launch_galk_rowlen(int64_t na, const int64_t *arp, const int32_t *acol, const int32_t *kq,
+                        int64_t *cstart, int64_t *rowlen, int64_t *blocksz, hipStream_t s);
+void launch_galk_pattern(int64_t na, const int32_t *kq, const int64_t *coff, const int64_t *arp,
+                         const int32_t *acol, const int64_t *base, const int64_t *rowlen,
+                         int64_t *rowptr, int32_t *col, hipStream_t s);
+void launch_galk_numeric(int K, int64_t annz, const int32_t *acrow, const int32_t *acol,
+                         const int32_t *amirror, const int64_t *gl_ptr, const int32_t *gl_idx,
+                         const int32_t *gl_row, const int32_t *fcol, const double *fval,
+                         const int32_t *slot, const double *Q, const int32_t *kq,
+                         const int64_t *coff, const int64_t *crp, const int64_t *cstart,
+                         double *cval, float *cval32, hipStream_t s);
+template <class T>
+void launch_restrict_k(int64_t na, int K, const int32_t *kq, const int64_t *coff,
+                       const int64_t *ap, const int32_t *mem, const T *Q, const T *res, T *rc,
+                       const int *done, hipStream_t s);
+template <class T>
+void launch_prolong_k(int64_t n, int K, const int32_t *agg, const int32_t *slot,
+                      const int32_t *kq, const int64_t *coff, const T *Q, const T *zc, T *z,
+                      const int *done, hipStream_t s);
+
 }  // namespace mgpbd

@@ -416,13 +416,17 @@ void Solver::colour_level(int l) {
 
 // near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|)
 // of its body, then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
+// Near-kernel candidates of level 0 (Sec. 4.3): each from its own random
+// start (candidate k uses indices k 2^40 + row), then the Gauss-Seidel sweeps
+// on A x = 0; B is [n][K].
 void Solver::candidate0() {
   Level &L = *lev[0];
   const int64_t n = L.n;
   const int ns = (int)L.seg.size() - 1;
-  L.B.alloc(n);
+  const int K = opt.n_cand;
+  L.B.alloc(n * K);
   if (opt.b_mode == 1) {
-    launch_fill(n, 1.0, L.B.p, st);
+    launch_fill(n * K, 1.0, L.B.p, st);
     return;
   }
   CsrView<double> A = L.view();
@@ -430,12 +434,19 @@ void Solver::candidate0() {
   amax.reserve(ns);
   MG_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * ns, st));
   launch_s_absmax(t, L.rowptr.p, L.val.p, amax.p, st);
-  launch_s_candidate_init(t, stream_salt(opt.seed, kStreamNearKernel), amax.p, L.B.p, st);
   if (opt.smoother != 2) colour_level(0);   // (the Gauss-Seidel smoother coloured it already)
-  for (int s = 0; s < opt.gs_sweeps; ++s)
-    for (int c = 0; c < L.n_colors; ++c)
-      launch_gs_color(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
-                      L.diag.p, L.B.p, st);
+  DevBuf<double> x;
+  if (K > 1) x.alloc(n);
+  for (int k = 0; k < K; ++k) {
+    double *v = K > 1 ? x.p : L.B.p;
+    launch_s_candidate_init(t, stream_salt(opt.seed, kStreamNearKernel), amax.p,
+                            (uint64_t)k << 40, v, st);
+    for (int s = 0; s < opt.gs_sweeps; ++s)
+      for (int c = 0; c < L.n_colors; ++c)
+        launch_gs_color(L.color_off[c + 1] - L.color_off[c], L.color_rows.p + L.color_off[c], A,
+                        L.diag.p, v, st);
+    if (K > 1) launch_put_column(n, K, k, x.p, L.B.p, st);
+  }
   MG_HIP(hipStreamSynchronize(st));
 }
 
@@ -449,6 +460,7 @@ void Solver::build_members(int l) {
   scan_exclusive_i32_to_i64(itmp.p, L.agg_ptr.p, na, scan_tmp, st);
   MG_HIP(hipMemsetAsync(itmp.p, 0, sizeof(int32_t) * na, st));
   int64_t nmem = read_dev(L.agg_ptr.p + na, st, pinned);
+  L.nmem = nmem;
   L.agg_mem.alloc(std::max<int64_t>(nmem, 1));
   launch_scatter_members(L.n, L.agg.p, L.agg_ptr.p, itmp.p, L.agg_mem.p, st);
   launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
@@ -499,9 +511,107 @@ void Solver::galerkin_symbolic(int l) {
   if (mixed()) C.val32.alloc(C.nnz);
 }
 
+// K > 1: modified Gram-Schmidt QR of every aggregate's candidates (member
+// slots, Q, kq, coff) and the next level's candidates from R. Returns the
+// number of coarse unknowns.
+int64_t Solver::qr_level(int l) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  const int K = opt.n_cand;
+  const int64_t na = L.n_agg;
+  L.K = K;
+  L.slot.alloc(std::max<int64_t>(L.n, 1));
+  launch_fill_i32(L.n, -1, L.slot.p, st);
+  launch_member_slots(L.nmem, L.agg_mem.p, L.slot.p, st);
+  L.Q.alloc(std::max<int64_t>(L.nmem * K, 1));
+  L.kq.alloc(std::max<int64_t>(na, 1));
+  DevBuf<double> R;
+  R.alloc(std::max<int64_t>(na * K * K, 1));
+  launch_qr_agg(na, K, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.Q.p, R.p, L.kq.p, st);
+  L.coff.alloc(na + 1);
+  scan_exclusive_i32_to_i64(L.kq.p, L.coff.p, na, scan_tmp, st);
+  const int64_t nc = read_dev(L.coff.p + na, st, pinned);
+  C.B.alloc(std::max<int64_t>(nc * K, 1));
+  launch_scatter_r(na, K, L.kq.p, L.coff.p, R.p, C.B.p, st);
+  if (mixed()) {
+    L.Q32.alloc(std::max<int64_t>(L.nmem * K, 1));
+    launch_d2f(L.nmem * K, L.Q.p, L.Q32.p, nullptr, st);
+  }
+  MG_HIP(hipStreamSynchronize(st));
+  return nc;
+}
+
+// K > 1: the aggregate-level pattern of the next level (the K = 1 symbolic
+// kernels), then each aggregate entry expanded into its block of unknowns.
+void Solver::galerkin_symbolic_k(int l) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  const int64_t na = L.n_agg;
+  CsrView<double> A = L.view();
+  ltmp.reserve(na + 1);
+  ltmp2.reserve(na + 1);
+  reset_flags();
+  launch_gal_count(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, ltmp.p, ltmp2.p,
+                   flags.p + kFOverflow, st);
+  MG_REQUIRE(read_flag(kFOverflow) == 0, MGPBD_E_SETUP,
+             "a coarse row has more distinct columns than the symbolic table holds");
+  L.arp.alloc(na + 1);
+  scan_exclusive_i64(ltmp.p, L.arp.p, na, scan_tmp, st);
+  DevBuf<int64_t> eoff;
+  eoff.alloc(na + 1);
+  scan_exclusive_i64(ltmp2.p, eoff.p, na, scan_tmp, st);
+  L.annz = read_dev(L.arp.p + na, st, pinned);
+  const int64_t nlist = read_dev(eoff.p + na, st, pinned);
+  MG_REQUIRE(nlist < (int64_t)INT32_MAX * 2, MGPBD_E_SETUP, "Galerkin list too long");
+  const int64_t an = std::max<int64_t>(L.annz, 1);
+  L.acol.alloc(an);
+  L.acrow.alloc(an);
+  L.amirror.alloc(an);
+  L.gl_ptr.alloc(L.annz + 1);
+  L.gl_idx.alloc(std::max<int64_t>(nlist, 1));
+  L.gl_row.alloc(std::max<int64_t>(nlist, 1));
+  reset_flags();
+  launch_gal_fill(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, L.arp.p, eoff.p, L.acol.p, L.acrow.p,
+                  L.gl_ptr.p, L.gl_idx.p, L.gl_row.p, flags.p + kFOverflow, st);
+  MG_HIP(hipMemcpyAsync(L.gl_ptr.p + L.annz, eoff.p + na, sizeof(int64_t),
+                        hipMemcpyDeviceToDevice, st));
+  launch_gal_mirror(L.annz, L.acrow.p, L.acol.p, L.arp.p, L.amirror.p, flags.p + kFMirror, st);
+  int *h = static_cast<int *>(pinned);
+  MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  MG_REQUIRE(h[kFOverflow] == 0, MGPBD_E_SETUP, "symbolic Galerkin table overflow");
+  MG_REQUIRE(h[kFMirror] == 0, MGPBD_E_SETUP, "coarse pattern is not symmetric");
+  // expansion into unknowns
+  L.cstart.alloc(an);
+  DevBuf<int64_t> rowlen, blocksz, base;
+  rowlen.alloc(std::max<int64_t>(na, 1));
+  blocksz.alloc(std::max<int64_t>(na, 1));
+  base.alloc(na + 1);
+  launch_galk_rowlen(na, L.arp.p, L.acol.p, L.kq.p, L.cstart.p, rowlen.p, blocksz.p, st);
+  scan_exclusive_i64(blocksz.p, base.p, na, scan_tmp, st);
+  C.n = read_dev(L.coff.p + na, st, pinned);
+  C.nnz = read_dev(base.p + na, st, pinned);
+  MG_REQUIRE(C.nnz < (int64_t)INT32_MAX * 4, MGPBD_E_SETUP, "coarse level too large");
+  C.rowptr.alloc(C.n + 1);
+  C.col.alloc(std::max<int64_t>(C.nnz, 1));
+  launch_galk_pattern(na, L.kq.p, L.coff.p, L.arp.p, L.acol.p, base.p, rowlen.p, C.rowptr.p,
+                      C.col.p, st);
+  MG_HIP(hipMemcpyAsync(C.rowptr.p + C.n, base.p + na, sizeof(int64_t), hipMemcpyDeviceToDevice,
+                        st));
+  C.val.alloc(std::max<int64_t>(C.nnz, 1));
+  if (mixed()) C.val32.alloc(std::max<int64_t>(C.nnz, 1));
+  MG_HIP(hipStreamSynchronize(st));
+}
+
 void Solver::galerkin_numeric(int l) {
   Level &L = *lev[l];
   Level &C = *lev[l + 1];
+  if (L.K > 1) {
+    launch_galk_numeric(L.K, L.annz, L.acrow.p, L.acol.p, L.amirror.p, L.gl_ptr.p, L.gl_idx.p,
+                        L.gl_row.p, L.col.p, L.val.p, L.slot.p, L.Q.p, L.kq.p, L.coff.p,
+                        C.rowptr.p, L.cstart.p, C.val.p, mixed() ? C.val32.p : nullptr, st);
+    return;
+  }
   launch_gal_numeric(C.nnz, C.crow.p, C.col.p, C.mirror.p, L.gl_ptr.p, L.gl_idx.p, L.gl_row.p,
                      L.col.p, L.val.p, L.p.p, C.val.p, mixed() ? C.val32.p : nullptr, st);
 }
@@ -608,20 +718,31 @@ void Solver::setup() {
     build_members(l);
     lev.emplace_back(new Level());
     Level &C = *lev[l + 1];
-    L.p.alloc(L.n);
-    if (mixed()) L.p32.alloc(L.n);
-    launch_fill(L.n, 0.0, L.p.p, st);
-    C.B.alloc(L.n_agg);
-    launch_normalize(L.n_agg, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.p.p, nullptr, C.B.p, st);
-    if (mixed()) launch_d2f(L.n, L.p.p, L.p32.p, nullptr, st);
-    galerkin_symbolic(l);
+    // first coarse unknown of each segment's aggregates
+    std::vector<int64_t> cfirst = first;
+    if (opt.n_cand > 1) {
+      qr_level(l);
+      std::vector<int64_t> coffh(L.n_agg + 1);
+      L.coff.download(coffh.data(), L.n_agg + 1, st);
+      MG_HIP(hipStreamSynchronize(st));
+      for (int k = 0; k <= ns; ++k) cfirst[k] = coffh[first[k]];
+      galerkin_symbolic_k(l);
+    } else {
+      L.p.alloc(L.n);
+      if (mixed()) L.p32.alloc(L.n);
+      launch_fill(L.n, 0.0, L.p.p, st);
+      C.B.alloc(L.n_agg);
+      launch_normalize(L.n_agg, L.agg_ptr.p, L.agg_mem.p, L.B.p, L.p.p, nullptr, C.B.p, st);
+      if (mixed()) launch_d2f(L.n, L.p.p, L.p32.p, nullptr, st);
+      galerkin_symbolic(l);
+    }
     galerkin_numeric(l);
     L.has_next = true;
     C.seg.assign(1, 0);
     C.body.clear();
     for (int k = 0; k < ns; ++k) {
       if (L.terminal[k]) continue;
-      const int64_t na_k = first[k + 1] - first[k];
+      const int64_t na_k = cfirst[k + 1] - cfirst[k];
       const int64_t nk = L.seg[k + 1] - L.seg[k];
       C.seg.push_back(C.seg.back() + na_k);
       C.body.push_back(L.body[k]);
@@ -674,6 +795,7 @@ template <> struct Buf<double> {
   static const double *cheb(const Level &L) { return L.cheb.p; }
   static double *dir(Level &L) { return L.dir.p; }
   static const double *p(const Level &L) { return L.p.p; }
+  static const double *Q(const Level &L) { return L.Q.p; }
 };
 template <> struct Buf<float> {
   static DevBuf<float> &z(Level &L) { return L.z32; }
@@ -686,6 +808,7 @@ template <> struct Buf<float> {
   static const float *cheb(const Level &L) { return L.cheb32.p; }
   static float *dir(Level &L) { return L.dir32.p; }
   static const float *p(const Level &L) { return L.p32.p; }
+  static const float *Q(const Level &L) { return L.Q32.p; }
 };
 
 template <>
@@ -724,14 +847,37 @@ void Solver::gs_vcycle(int l, const T *r, T *z) {
     T *res = Buf<T>::res(L).p;
     if (const MfView<T> *M = level_mf<T>(l)) launch_mf_residual<T>(*M, r, z, res, done, st);
     else launch_residual<T>(A, r, z, res, done, st);
-    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, pl, res, rc, done, st);
+    (void)pl;
+    restrict_to<T>(l, res, rc);
     vcycle<T>(l + 1, rc, ec);
-    launch_prolong<T>(L.n, L.agg.p, pl, ec, z, done, st);
+    prolong_from<T>(l, ec, z);
   }
   for (int k = 0; k < opt.post_sweeps; ++k) sweep(true);
   if (!L.jobs.empty())
     launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
                                 Ainv.p, r, z, done, st);
+}
+
+// transfers between level l and l + 1: P^T (restriction) and P (prolongation
+// added to z); one value per row, or the Q blocks when K > 1
+template <class T>
+void Solver::restrict_to(int l, const T *res, T *rc) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  if (L.K > 1)
+    launch_restrict_k<T>(L.n_agg, L.K, L.kq.p, L.coff.p, L.agg_ptr.p, L.agg_mem.p, Buf<T>::Q(L),
+                         res, rc, done_ptr(), st);
+  else
+    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, rc, done_ptr(), st);
+}
+template <class T>
+void Solver::prolong_from(int l, const T *ec, T *z) {
+  Level &L = *lev[l];
+  if (L.K > 1)
+    launch_prolong_k<T>(L.n, L.K, L.agg.p, L.slot.p, L.kq.p, L.coff.p, Buf<T>::Q(L), ec, z,
+                        done_ptr(), st);
+  else
+    launch_prolong<T>(L.n, L.agg.p, Buf<T>::p(L), ec, z, done_ptr(), st);
 }
 
 template <class T>
@@ -804,9 +950,10 @@ void Solver::vcycle(int l, const T *r, T *z) {
     T *res = Buf<T>::res(L).p;
     if (M) launch_mf_residual<T>(*M, r, cur, res, done, st);
     else launch_residual<T>(A, r, cur, res, done, st);
-    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, pl, res, rc, done, st);
+    (void)pl;
+    restrict_to<T>(l, res, rc);
     vcycle<T>(l + 1, rc, ec);
-    launch_prolong<T>(L.n, L.agg.p, pl, ec, cur, done, st);
+    prolong_from<T>(l, ec, cur);
   }
   for (int k = 0; k < post; ++k) {
     T *o = next();

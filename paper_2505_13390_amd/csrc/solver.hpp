@@ -60,9 +60,19 @@ struct Level {
   DevBuf<int32_t> agg_mem;
   DevBuf<double> p, B;
   DevBuf<float> p32;
-  // fine entries feeding each entry of the next level, ascending fine order
+  // fine entries feeding each entry of the next level (of each aggregate block
+  // when K > 1), ascending fine order
   DevBuf<int64_t> gl_ptr;
   DevBuf<int32_t> gl_idx, gl_row;
+  // K > 1 candidates: B is [n][K]; P row of member slot m is Q[m][0..kq-1];
+  // the next level's aggregate-level pattern (entries, their rows and
+  // mirrors, each block's start within the expanded rows)
+  int K = 1;
+  int64_t nmem = 0, annz = 0;
+  DevBuf<int32_t> kq, slot, acol, acrow, amirror;
+  DevBuf<int64_t> coff, arp, cstart;
+  DevBuf<double> Q;
+  DevBuf<float> Q32;
   // multicolour order (level 0 near-kernel sweeps)
   int n_colors = 0;
   std::vector<int64_t> color_off;
@@ -176,6 +186,10 @@ class Solver {
   void build_members(int l);
   void galerkin_symbolic(int l);
   void galerkin_numeric(int l);
+  int64_t qr_level(int l);
+  void galerkin_symbolic_k(int l);
+  template <class T> void restrict_to(int l, const T *res, T *rc);
+  template <class T> void prolong_from(int l, const T *ec, T *z);
   void power_omega(int l);
   void tune_lanes(int l);
   void chebyshev_table(int l);
