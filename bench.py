@@ -187,6 +187,9 @@ def main():
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev", "gs"],
                     help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default), Chebyshev or "
                          "multicolour Gauss-Seidel")
+    ap.add_argument("--candidates", type=int, default=1,
+                    help="near-kernel candidates per level (Sec. 4.3 generates six); 1 is the "
+                         "one-candidate hierarchy of the headline line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -217,7 +220,7 @@ def main():
     if args.lmax_scale is None:
         args.lmax_scale = 1.5 if args.config.startswith("A") else 1.05
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
-                                  lmax_scale=args.lmax_scale,
+                                  lmax_scale=args.lmax_scale, n_cand=args.candidates,
                                   profile_spmv=0 if args.no_profile else 1,
                                   matrix_free=1 if args.fine == "mf" else 0,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
@@ -308,6 +311,8 @@ def main():
                                  "timing": "HIP events around each kernel of every PCG product"}}
         if parts:
             roof["timed_region"]["parts"] = parts
+    nl = B.mgpbd_num_levels(body.ctx)
+    lv = [B.mgpbd_get_level(body.ctx, l) for l in range(nl)]
     out = {
         "metric": METRIC, "value": value, "unit": "constraint-DOF*iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_frame,
@@ -318,10 +323,12 @@ def main():
                    "iters_per_frame": n_iters, "precision": args.precision,
                    "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
                    "smoother": args.smoother, "reuse_interval": args.reuse, "tol": 1e-6,
-                   "lmax_scale": args.lmax_scale,
+                   "lmax_scale": args.lmax_scale, "candidates": args.candidates,
                    "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
-                   "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps},
+                   "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps,
+                   "levels": [x["n"] for x in lv],
+                   "operator_complexity": round(sum(x["nnz"] for x in lv) / lv[0]["nnz"], 4)},
         "roofline": roof,
     }
     body.close()
