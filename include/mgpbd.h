@@ -233,7 +233,8 @@ mgpbd_status mgpbd_get_level(const mgpbd_ctx *ctx, int32_t l, int64_t *n, int64_
                              double *omega, int64_t *n_agg);
 /* aggregate id of every row of level l (-1 = isolated); host int32 [n_l] */
 mgpbd_status mgpbd_get_aggregates(const mgpbd_ctx *ctx, int32_t l, int32_t *agg);
-/* prolongator value and near-kernel candidate of every row of level l; host FP64 [n_l] */
+/* prolongator value and near-kernel candidate of every row of level l; host FP64 [n_l]
+   (one candidate only: E_STATE when n_cand > 1, see mgpbd_get_qr) */
 mgpbd_status mgpbd_get_transfer(const mgpbd_ctx *ctx, int32_t l, double *p, double *B);
 /* sorted CSR of level l: host rowptr [n+1], col [nnz], val [nnz]; any may be NULL */
 mgpbd_status mgpbd_get_matrix(const mgpbd_ctx *ctx, int32_t l, int64_t *rowptr, int32_t *col,

@@ -464,9 +464,6 @@ void Solver::build_members(int l) {
   L.agg_mem.alloc(std::max<int64_t>(nmem, 1));
   launch_scatter_members(L.n, L.agg.p, L.agg_ptr.p, itmp.p, L.agg_mem.p, st);
   launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
-  // lanes per aggregate of the fused matrix-free residual + restriction
-  const double mean = na ? (double)nmem / (double)na : 1.0;
-  L.rlanes = mean <= 16.0 ? 8 : mean <= 32.0 ? 16 : mean <= 64.0 ? 32 : 64;
 }
 
 void Solver::galerkin_symbolic(int l) {

@@ -48,6 +48,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.spmv_tile == 0 and o.spmv_lanes == 0
     assert o.matrix_free == 1
     assert o.smoother == 0
+    assert o.n_cand == 1
 
 
 def test_null_arguments_rejected_without_device_work():
@@ -58,3 +59,5 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.mgpbd_step(None, None, None, None, None, None, None, 1, None) == binding.E_INVALID_ARG
     assert lib.mgpbd_num_levels(None, None) == binding.E_INVALID_ARG
     assert lib.mgpbd_last_error(None) == b"null context"
+    assert lib.mgpbd_apply(None, None, None) == binding.E_INVALID_ARG
+    assert lib.mgpbd_get_qr(None, 0, None, None, None, None) == binding.E_INVALID_ARG

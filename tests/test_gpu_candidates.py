@@ -145,3 +145,24 @@ def test_candidate_count_validated():
         with pytest.raises(B.MgpbdError):
             B.mgpbd_create(w.rest, w.inv_mass, w.tets, w.edges, w.vol_tet, w.alpha, w.dt,
                            w.gravity, go)
+
+
+@pytest.mark.parametrize("smoother", [1, 2])
+def test_six_candidates_with_other_smoothers(smoother):
+    w = W.tiny_beam(16, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8)
+    sim, body, pos, vel, ores, gres = run_both(w, 3, force_from_oracle=True, n_cand=6,
+                                               smoother=smoother, coarse_max=60)
+    err = rel_pos_err(body.positions(), pos)
+    log("K=6 smoother %d: position err %.3e iters %s" % (smoother, err,
+                                                          ores[0]["pcg_iters"].tolist()))
+    assert err <= 1e-9
+
+
+def test_six_candidates_on_arap_rows():
+    w = W.arap_beam(16, 4, 4, seed=71, squash=0.05)
+    sim, body, pos, vel, ores, gres = run_both(w, 1, force_from_oracle=True, n_cand=6,
+                                               lmax_scale=1.5, coarse_max=60)
+    compare_hierarchy_k(sim.hier(), body.ctx, 6, "ARAP K=6")
+    err = rel_pos_err(body.positions(), pos)
+    log("ARAP K=6: position err %.3e" % err)
+    assert err <= 1e-9
