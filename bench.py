@@ -340,6 +340,21 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes_read"] = src.numel() * 8
         del src, dst
+    if roof is not None:
+        # what a plain device copy reaches on this GPU (1 GiB read + 1 GiB
+        # written per copy, far beyond the 256 MB Infinity Cache)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        roof["copy_GBps"] = round(2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del src, dst
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w, args.lmax_scale)

@@ -166,3 +166,29 @@ def test_six_candidates_on_arap_rows():
     err = rel_pos_err(body.positions(), pos)
     log("ARAP K=6: position err %.3e" % err)
     assert err <= 1e-9
+
+
+def test_solve_entry_with_six_candidates():
+    """mgpbd_solve on a caller matrix with six candidates: the same hierarchy
+    as the oracle's (bit for bit) and the same solution to the tolerance."""
+    import scipy.sparse as sp
+    w = W.perturbed(W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8), 0.01)
+    sim = O.Sim(w)
+    val, b = sim.assemble(w.x0)
+    rp, col = sim.pattern()
+    oo, go = opts(coarse_max=60, n_cand=6)
+    h = O.Hier.build(rp, col, val, oo)
+    xo, st = h.pcg(b, 1e-8, 1000)
+    ctx = B.mgpbd_solver_create(go)
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")
+    xg = torch.zeros(sim.m, dtype=torch.float64, device="cuda")
+    r = B.mgpbd_solve(ctx, dev(rp, torch.int64), dev(col, torch.int32), dev(val, torch.float64),
+                      dev(b, torch.float64), 1e-8, xg)
+    log("K=6 solve iters oracle", st["iters"], "gpu", r["iters"])
+    assert r["status"] == B.OK
+    compare_hierarchy_k(h, ctx, 6, "solve K=6")
+    x = xg.cpu().numpy()
+    A = sp.csr_matrix((val, col, rp))
+    assert np.linalg.norm(A @ x - b) <= 1.01e-7 * np.linalg.norm(b)
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+    B.mgpbd_destroy(ctx)
