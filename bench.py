@@ -112,11 +112,12 @@ def bench_batch(args, B, W):
     block-diagonal system (default) or one after another (--sequential)."""
     import numpy as np
     import torch
-    ws = W.batch_c3()
+    ws = W.batch_c3() if args.config == "C3" else W.stiff_c4(copies=args.copies)
     n_iters = args.iters or ws[0].iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   matrix_free=1 if args.fine == "mf" else 0,
+                                  lmax_scale=args.lmax_scale or 1.05,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
@@ -142,6 +143,11 @@ def bench_batch(args, B, W):
         its = [int(x["pcg_iters"].sum()) for x in r]
         print("frame %d: %.1f ms, pcg iterations per body (sum over the frame) min %d max %d"
               % (args.warmup + f, ms, min(its), max(its)), file=sys.stderr, flush=True)
+        if len(r) <= 8:
+            for k, x in enumerate(r):
+                print("  body %d: pcg iters %s, last ratio %.2e"
+                      % (k, x["pcg_iters"].tolist(), float(x["pcg_ratio"][-1])),
+                      file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dof_iters = sum(float(m) * float(x["pcg_iters"].sum()) for r in res for m, x in zip(rows, r))
@@ -155,7 +161,9 @@ def bench_batch(args, B, W):
         "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == B.PREC_FP64 else "f32 V-cycle / f64 PCG", "data": "synthetic",
-        "config": {"workload": "batch_64_beams_n4-24", "bodies": len(ws), "rows": sum(rows),
+        "config": {"workload": ("batch_64_beams_n4-24" if args.config == "C3"
+                                else "stiff_ellipsoid_x%d" % len(ws)),
+                   "bodies": len(ws), "rows": sum(rows),
                    "mode": "sequential contexts" if args.sequential else "one batch",
                    "iters_per_frame": n_iters, "precision": args.precision,
                    "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
@@ -169,7 +177,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3", "A0", "A1"],
+    ap.add_argument("--copies", type=int, default=8,
+                    help="C4: copies of the stiff ellipsoid stepped as one batch")
+    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3", "C4", "A0", "A1"],
                     help="C3: the 64-beam batch; A0/A1: the ARAP beams (comparison runs, "
                          "not the headline line)")
     ap.add_argument("--lmax-scale", type=float, default=None,
@@ -210,8 +220,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.precision is None:
-        args.precision = "mixed" if args.config == "C3" else "fp64"
-    if args.config == "C3":
+        args.precision = "mixed" if args.config in ("C3", "C4") else "fp64"
+    if args.config in ("C3", "C4"):
         bench_batch(args, B, W)
         return
     w = W.CONFIGS[args.config]()
