@@ -201,7 +201,11 @@ def main():
                     help="near-kernel candidates per level (Sec. 4.3 generates six); 1 is the "
                          "one-candidate hierarchy of the headline line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--profile-frames", action="store_true",
+                    help="time each kernel of every PCG product inside the timed frames with HIP "
+                         "events (launches kernels directly instead of replaying the graph, "
+                         "which slows the frames by a few percent)")
+    ap.add_argument("--no-profile", action="store_true", help="(accepted; the default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed frames, copy a 1 GiB buffer 3 times (reference "
                          "kernel of known size for the HBM byte counters)")
@@ -231,7 +235,7 @@ def main():
         args.lmax_scale = 1.5 if args.config.startswith("A") else 1.05
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   lmax_scale=args.lmax_scale, n_cand=args.candidates,
-                                  profile_spmv=0 if args.no_profile else 1,
+                                  profile_spmv=1 if args.profile_frames else 0,
                                   matrix_free=1 if args.fine == "mf" else 0,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
@@ -261,66 +265,67 @@ def main():
     value = dof_iters / pcg_s
     spmv_calls = sum(r["spmv_calls"] for r in res)
     spmv_ms = sum(r["spmv_ms"] for r in res)
-    roof = None
+    # the fine-level product of PCG (same context, same kernels) 200 times back
+    # to back on the context's stream, a torch stream of default priority so
+    # that torch's events see the launches
+    reps = 200
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    B.mgpbd_set_stream(body.ctx, stream.cuda_stream)
+    xp = torch.randn(body.m, dtype=torch.float64, device="cuda")
+    yp = torch.empty_like(xp)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        B.mgpbd_apply(body.ctx, xp, yp)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        B.mgpbd_apply(body.ctx, xp, yp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    avg_ms = e0.elapsed_time(e1) / reps
+    B.mgpbd_set_stream(body.ctx, 0)
+    del xp, yp
+    traffic = None
+    if args.fine == "mf":
+        ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
+        nar = int(w.arap_tet.shape[0])
+        gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol + 4 * nar, ne, nvol, nar)
+        nbytes = gb + rb
+        kname = ("fine-level A p, matrix-free: k_mf_gather + k_mf_rows<OpPcgDot> "
+                 "(one launch each)")
+        counters = {"C1": "k_mf_apply_beam32x32x128_counters.txt",
+                    "A1": "k_mf_apply_arap32x32x128_counters.txt"}.get(args.config)
+        if counters and prec == B.PREC_FP64:
+            traffic = measured_traffic(counters, MF_SOURCES)
+    else:
+        gb = rb = None
+        nbytes = spmv_bytes(body.m, body.nnz)
+        kname = "fine-level A p, CSR: k_rows/k_stream<OpPcgDot>"
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": kname, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
+            "timing": "%d back-to-back products after the timed frames, HIP events on "
+                      "their stream" % reps}
+    if gb is not None:
+        roof["bytes_parts"] = {"k_mf_gather": gb, "k_mf_rows<OpPcgDot>": rb}
     if spmv_calls:
-        # per-kernel HIP events around every PCG product of the timed frames
-        # (each event pair adds a launch gap to the kernel it brackets)
+        # --profile-frames: HIP events around each kernel of every PCG product of
+        # the timed frames (kernels launched directly, not from the graph)
         loop_ms = spmv_ms / spmv_calls
         first_ms = sum(r["spmv_first_ms"] for r in res) / spmv_calls
-        # the same product, same kernels, back to back on the context's stream
-        # (a torch stream of default priority, so that torch's events see the
-        # launches)
-        reps = 200
-        stream = torch.cuda.Stream()
-        torch.cuda.synchronize()
-        B.mgpbd_set_stream(body.ctx, stream.cuda_stream)
-        xp = torch.randn(body.m, dtype=torch.float64, device="cuda")
-        yp = torch.empty_like(xp)
-        torch.cuda.synchronize()
-        for _ in range(5):
-            B.mgpbd_apply(body.ctx, xp, yp)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            B.mgpbd_apply(body.ctx, xp, yp)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        avg_ms = e0.elapsed_time(e1) / reps
-        B.mgpbd_set_stream(body.ctx, 0)
-        del xp, yp
-        traffic = None
-        if args.fine == "mf":
-            ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
-            nar = int(w.arap_tet.shape[0])
-            gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol + 4 * nar, ne, nvol, nar)
-            nbytes = gb + rb
-            kname = ("fine-level A p, matrix-free: k_mf_gather + k_mf_rows<OpPcgDot> "
-                     "(one launch each)")
-            parts = {"k_mf_gather": {"bytes": gb, "avg_ms": round(first_ms, 5),
-                                     "GB/s": round(gb / (first_ms * 1e-3) / 1e9, 1)},
-                     "k_mf_rows<OpPcgDot>": {"bytes": rb, "avg_ms": round(loop_ms - first_ms, 5),
-                                             "GB/s": round(rb / ((loop_ms - first_ms) * 1e-3)
-                                                           / 1e9, 1)}}
-            counters = {"C1": "k_mf_apply_beam32x32x128_counters.txt",
-                        "A1": "k_mf_apply_arap32x32x128_counters.txt"}.get(args.config)
-            if counters and prec == B.PREC_FP64:
-                traffic = measured_traffic(counters, MF_SOURCES)
-        else:
-            nbytes = spmv_bytes(body.m, body.nnz)
-            kname = "fine-level A p, CSR: k_rows/k_stream<OpPcgDot>"
-            parts = None
-        ach = nbytes / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": kname, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5),
-                "timing": "%d back-to-back products after the timed frames, HIP events on "
-                          "their stream" % reps,
-                "timed_region": {"products": int(spmv_calls), "avg_ms": round(loop_ms, 5),
-                                 "GB/s": round(nbytes / (loop_ms * 1e-3) / 1e9, 1),
-                                 "timing": "HIP events around each kernel of every PCG product"}}
-        if parts:
-            roof["timed_region"]["parts"] = parts
+        roof["timed_region"] = {"products": int(spmv_calls), "avg_ms": round(loop_ms, 5),
+                                "GB/s": round(nbytes / (loop_ms * 1e-3) / 1e9, 1),
+                                "timing": "HIP events around each kernel of every PCG product"}
+        if gb is not None:
+            roof["timed_region"]["parts"] = {
+                "k_mf_gather": {"bytes": gb, "avg_ms": round(first_ms, 5),
+                                "GB/s": round(gb / (first_ms * 1e-3) / 1e9, 1)},
+                "k_mf_rows<OpPcgDot>": {"bytes": rb, "avg_ms": round(loop_ms - first_ms, 5),
+                                        "GB/s": round(rb / ((loop_ms - first_ms) * 1e-3) / 1e9,
+                                                      1)}}
     nl = B.mgpbd_num_levels(body.ctx)
     lv = [B.mgpbd_get_level(body.ctx, l) for l in range(nl)]
     out = {
