@@ -219,7 +219,8 @@ def ellipsoid(nx: int, ny: int, nz: int, *, seed: int, semi=(0.5, 0.5, 1.0),
 
 
 # --------------------------------------------------------------------------
-# The five workloads (sizes and recipes stated in the design doc).
+# The named workloads: the edge beam, the edge + volume beam, the muscle, the
+# 64-beam batch, the stiff copies and the two ARAP beams.
 # --------------------------------------------------------------------------
 def beam_c0(seed: int = BASE_SEED + 0) -> Workload:
     """8x8x32 cube beam, edges only, compliance 1e-8, 1 frame x 20 iterations."""
