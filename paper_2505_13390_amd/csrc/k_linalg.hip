@@ -271,10 +271,15 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t na, const int64_t *
 
 template <class T>
 void launch_restrict(int64_t na, const int64_t *ap, const int32_t *mem, const T *p, const T *res,
-                     T *rc, const int *done, hipStream_t s) {
+                     T *rc, int lanes, const int *done, hipStream_t s) {
   if (na == 0) return;
-  int grid = grid_for(na * 8, kBlock);
-  k_restrict<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done);
+  const int grid = grid_for(na * lanes, kBlock);
+  switch (lanes) {
+    case 64: k_restrict<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
+    case 32: k_restrict<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
+    case 16: k_restrict<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
+    default: k_restrict<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
+  }
 }
 
 template <class T>
@@ -501,7 +506,7 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
   template void launch_cheb<T>(const CsrView<T> &, const T *, const T *, const T *, const int32_t *, \
                                int, int, const T *, T *, T *, const int *, hipStream_t);            \
   template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
-                                   T *, const int *, hipStream_t);                                  \
+                                   T *, int, const int *, hipStream_t);                             \
   template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \
                                   hipStream_t);                                                     \
   template void launch_copy_t<T>(int64_t, const T *, T *, const int *, hipStream_t);                \

@@ -60,10 +60,11 @@ template <class T> void launch_cheb_first(int64_t n, const T *r, const T *dinv, 
 template <class T> void launch_cheb(const CsrView<T> &A, const T *r, const T *dinv,
                                     const T *coef, const int32_t *rowseg, int steps, int k,
                                     const T *zi, T *d, T *zo, const int *done, hipStream_t s);
-// rc[a] = sum over members i of a (ascending) of p_i res_i
+// rc[a] = sum over members i of a of p_i res_i; `lanes` (8, 16, 32 or 64) lanes per
+// aggregate, each summing a strided share, then a fixed-tree lane sum
 template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
                                         const int32_t *agg_mem, const T *p, const T *res, T *rc,
-                                        const int *done, hipStream_t s);
+                                        int lanes, const int *done, hipStream_t s);
 // z_i += p_i ec[agg_i]
 template <class T> void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec,
                                        T *z, const int *done, hipStream_t s);

@@ -461,6 +461,11 @@ void Solver::build_members(int l) {
   MG_HIP(hipMemsetAsync(itmp.p, 0, sizeof(int32_t) * na, st));
   int64_t nmem = read_dev(L.agg_ptr.p + na, st, pinned);
   L.nmem = nmem;
+  // enough lanes per aggregate that each sums a handful of members: the
+  // member loads are scattered, so fewer and longer chains leave the loads
+  // waiting one after another
+  const double mean = na ? (double)nmem / (double)na : 1.0;
+  L.rlanes = mean <= 16.0 ? 8 : mean <= 48.0 ? 16 : mean <= 160.0 ? 32 : 64;
   L.agg_mem.alloc(std::max<int64_t>(nmem, 1));
   launch_scatter_members(L.n, L.agg.p, L.agg_ptr.p, itmp.p, L.agg_mem.p, st);
   launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
@@ -865,7 +870,8 @@ void Solver::restrict_to(int l, const T *res, T *rc) {
     launch_restrict_k<T>(L.n_agg, L.K, L.kq.p, L.coff.p, L.agg_ptr.p, L.agg_mem.p, Buf<T>::Q(L),
                          res, rc, done_ptr(), st);
   else
-    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, rc, done_ptr(), st);
+    launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, rc, L.rlanes,
+                       done_ptr(), st);
 }
 template <class T>
 void Solver::prolong_from(int l, const T *ec, T *z) {

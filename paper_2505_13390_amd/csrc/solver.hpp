@@ -54,6 +54,7 @@ struct Level {
   // transfer to the next level
   bool has_next = false;
   int64_t n_agg = 0;
+  int rlanes = 8;   // lanes per aggregate in the restriction (from the mean aggregate size)
   DevBuf<int32_t> agg;
   DevBuf<int64_t> agg_ptr;
   DevBuf<int32_t> agg_mem;
