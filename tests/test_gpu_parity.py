@@ -376,3 +376,29 @@ def test_apply_entry_matches_assembled_matrix(mf, arap):
     with pytest.raises(B.MgpbdError):
         B.mgpbd_apply(solver, xt, yt)
     B.mgpbd_destroy(solver)
+
+
+def test_solve_entry_mixed_precision_reaches_tolerance():
+    """mgpbd_solve with the FP32 V-cycle (flexible PCG): the same aggregates
+    as the FP64 oracle's setup and an FP64 true residual at the tolerance."""
+    import scipy.sparse as sp
+    w = W.perturbed(W.tiny_beam(12, 4, 4, volumes=True, alpha_edge=1e-8, alpha_vol=1e-8), 0.01)
+    sim = O.Sim(w)
+    val, b = sim.assemble(w.x0)
+    rp, col = sim.pattern()
+    oo, go = opts(coarse_max=60, precision=B.PREC_MIXED)
+    h = O.Hier.build(rp, col, val, oo)
+    ctx = B.mgpbd_solver_create(go)
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")
+    xg = torch.zeros(sim.m, dtype=torch.float64, device="cuda")
+    r = B.mgpbd_solve(ctx, dev(rp, torch.int64), dev(col, torch.int32), dev(val, torch.float64),
+                      dev(b, torch.float64), 1e-8, xg)
+    assert r["status"] == B.OK
+    for l in range(h.levels - 1):
+        assert np.array_equal(B.mgpbd_get_aggregates(ctx, l), h.transfer(l)[0])
+    x = xg.cpu().numpy()
+    A = sp.csr_matrix((val, col, rp))
+    rel = float(np.linalg.norm(A @ x - b) / np.linalg.norm(b))
+    log("mixed solve: %d iterations, true residual %.3e" % (r["iters"], rel))
+    assert rel <= 1.5e-8
+    B.mgpbd_destroy(ctx)
