@@ -197,6 +197,9 @@ def main():
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev", "gs"],
                     help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default), Chebyshev or "
                          "multicolour Gauss-Seidel")
+    ap.add_argument("--candidate", default="smoothed", choices=["smoothed", "ones"],
+                    help="near-kernel candidate: Gauss-Seidel-smoothed random vectors (Sec. 4.3, "
+                         "the default) or the all-ones vector (piecewise-constant P)")
     ap.add_argument("--candidates", type=int, default=1,
                     help="near-kernel candidates per level (Sec. 4.3 generates six); 1 is the "
                          "one-candidate hierarchy of the headline line")
@@ -235,6 +238,7 @@ def main():
         args.lmax_scale = 1.5 if args.config.startswith("A") else 1.05
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   lmax_scale=args.lmax_scale, n_cand=args.candidates,
+                                  b_mode=1 if args.candidate == "ones" else 0,
                                   profile_spmv=1 if args.profile_frames else 0,
                                   matrix_free=1 if args.fine == "mf" else 0,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
@@ -339,6 +343,7 @@ def main():
                    "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
                    "smoother": args.smoother, "reuse_interval": args.reuse, "tol": 1e-6,
                    "lmax_scale": args.lmax_scale, "candidates": args.candidates,
+                   "candidate": args.candidate,
                    "pcg_iters_per_solve": float(np.mean([r["pcg_iters"].mean() for r in res])),
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
                    "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps,

@@ -284,6 +284,22 @@ def test_cg_terminates_in_n_steps_small():
         assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-12)
 
 
+def test_pcg_error_decreases_in_the_energy_norm():
+    """CG minimises the A-norm of the error over growing Krylov spaces, so
+    with an SPD preconditioner (the V-cycle) the A-norm error of the k-th
+    iterate never increases with k (checked against a dense solve)."""
+    w, s, rp, col, val, b, h = small_hier()
+    A = dense(rp, col, val)
+    xs = np.linalg.solve(A, b)
+    prev = np.inf
+    for k in range(1, 40):
+        x, st = h.pcg(b, 0.0, 1000, force_iters=k)
+        e = x - xs
+        en = float(np.sqrt(e @ A @ e))
+        assert en <= prev * (1 + 1e-9) + 1e-14 * np.sqrt(xs @ A @ xs), (k, en, prev)
+        prev = en
+
+
 def test_direct_coarsest_single_level_converges_in_one_iteration():
     w = W.perturbed(W.tiny_beam(3, 2, 2, volumes=True), 0.02)
     s = O.Sim(w)
