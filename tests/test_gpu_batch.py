@@ -218,3 +218,27 @@ def test_batch_rejects_mismatched_members():
         B.mgpbd_batch_create([ba.ctx, bb.ctx])
     ba.close()
     bb.close()
+
+
+def test_apply_on_a_batch_context():
+    """mgpbd_apply on the batch's system context: all bodies' rows back to
+    back, equal to the block-diagonal assembled matrix up to summation order."""
+    import scipy.sparse as sp
+    ws = bodies()
+    _, go = opts(coarse_max=CMAX)
+    batch = B.Batch(ws, go)
+    batch.step(1)
+    rp, col, val = B.mgpbd_get_matrix(batch.ctx, 0)
+    A = sp.csr_matrix((val, col, rp))
+    m = rp.size - 1
+    assert m == sum(w.n_rows for w in ws)
+    x = np.random.default_rng(9).standard_normal(m)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    yt = torch.empty_like(xt)
+    B.mgpbd_apply(batch.ctx, xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    err = float((np.abs(y - A @ x) / (abs(A) @ np.abs(x))).max())
+    log("batch apply: %d rows, max row error %.3e of |A||x|" % (m, err))
+    batch.close()
+    assert err <= 1e-13
