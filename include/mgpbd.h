@@ -17,7 +17,8 @@
  *    torch.Tensor.data_ptr() of a cuda tensor on the current device). They
  *    are borrowed for the duration of the call only; work is ordered on the
  *    context's stream (mgpbd_set_stream; default: a stream the context creates) and every
- *    call returns after that work has completed.
+ *    call returns after that work has completed, except mgpbd_apply, which only
+ *    enqueues its kernels.
  *  - Arrays documented as "host" are ordinary CPU memory, read or written
  *    during the call only.
  *  - The library never frees caller memory; mgpbd_destroy frees everything
