@@ -75,8 +75,10 @@ def measured_traffic(name: str, sources):
         return None
 
 
-MF_SOURCES = ("paper_2505_13390_amd/csrc/k_mfree.hip", "paper_2505_13390_amd/csrc/mfree.hpp",
-              "paper_2505_13390_amd/csrc/rowops.hpp")
+# every file the matrix-free kernels are compiled from
+MF_SOURCES = tuple("paper_2505_13390_amd/csrc/" + f for f in (
+    "k_mfree.hip", "mfree.hpp", "rowops.hpp", "grad.hpp", "kernels.hpp", "devutil.hpp",
+    "common.hpp")) + ("include/mgpbd.h",)
 
 
 def cpu_baseline(w, lmax_scale: float):
