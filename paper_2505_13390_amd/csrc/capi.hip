@@ -213,6 +213,24 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
   S.spmv_ms = 0.0;
   S.spmv_first_ms = 0.0;
   launch_predict(nv, c->w.p, c->g, c->dt, xyz, vxyz, oxyz, st);
+  if (m == 0) {
+    // no constraint rows: every global iteration is empty, the frame is the
+    // semi-implicit Euler step alone
+    launch_velocity(nv, c->dt, xyz, oxyz, vxyz, st);
+    c->frame++;
+    const double ms = total.stop(st);
+    if (stats)
+      for (int k = 0; k < nb; ++k) {
+        stats[k].iters_done = 0;
+        stats[k].ms_setup = 0.0;
+        stats[k].ms_pcg = 0.0;
+        stats[k].ms_total = ms;
+        stats[k].spmv_calls = 0;
+        stats[k].spmv_ms = 0.0;
+        stats[k].spmv_first_ms = 0.0;
+      }
+    return;
+  }
   launch_fill(m, 0.0, c->lambda.p, st);
   Level &F = S.L0();
   std::vector<char> stopped(nb, 0);

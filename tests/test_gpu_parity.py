@@ -402,3 +402,25 @@ def test_solve_entry_mixed_precision_reaches_tolerance():
     log("mixed solve: %d iterations, true residual %.3e" % (r["iters"], rel))
     assert rel <= 1.5e-8
     B.mgpbd_destroy(ctx)
+
+
+def test_body_without_constraints_is_a_plain_euler_step():
+    """No constraint rows: every global iteration is empty and the frame is
+    the semi-implicit Euler step of Algorithm 1 alone, as in the oracle."""
+    w = W.tiny_beam(2, 1, 1)
+    w.edges = np.zeros((0, 2), np.int32)
+    w.vol_tet = np.zeros(0, np.int32)
+    w.alpha = np.zeros(0)
+    oo, go = opts()
+    sim = O.Sim(w, oo)
+    pos, vel = O.positions(w)
+    r = sim.step(pos, vel, 3)
+    assert r["status"] == 0
+    body = B.Body(w, go)
+    assert body.m == 0
+    for _ in range(2):
+        body.step(3)
+    sim.step(pos, vel, 3)
+    assert np.array_equal(body.positions(), pos)
+    assert np.array_equal(body.velocities(), vel)
+    body.close()
