@@ -414,11 +414,10 @@ void Solver::colour_level(int l) {
   MG_HIP(hipStreamSynchronize(st));
 }
 
-// near-kernel candidate of level 0 (Sec. 4.3): x0 uniform in (0, max |A_ij|)
-// of its body, then gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0
-// Near-kernel candidates of level 0 (Sec. 4.3): each from its own random
-// start (candidate k uses indices k 2^40 + row), then the Gauss-Seidel sweeps
-// on A x = 0; B is [n][K].
+// Near-kernel candidates of level 0 (Sec. 4.3): each starts uniform in
+// (0, max |A_ij| of its body), drawn with indices k 2^40 + row for candidate
+// k, then takes gs_sweeps multicolour Gauss-Seidel sweeps on A x = 0; B is
+// [n][K].
 void Solver::candidate0() {
   Level &L = *lev[0];
   const int64_t n = L.n;

@@ -242,3 +242,45 @@ def test_apply_on_a_batch_context():
     log("batch apply: %d rows, max row error %.3e of |A||x|" % (m, err))
     batch.close()
     assert err <= 1e-13
+
+
+def empty_body(seed):
+    """A body with vertices but no constraint rows (all rows removed)."""
+    w = W.tiny_beam(3, 2, 1, seed=seed)
+    w.edges = np.zeros((0, 2), np.int32)
+    w.vol_tet = np.zeros(0, np.int32)
+    w.alpha = np.zeros(0)
+    w.name = "empty"
+    return w
+
+
+@pytest.mark.parametrize("mf,smoother", [(1, 0), (0, 0), (1, 1)])
+def test_batch_with_a_body_without_constraints(mf, smoother):
+    """A member without rows sits in the batch as an empty segment: it takes
+    the semi-implicit Euler step of Algorithm 1 (bit for bit, as in the
+    oracle) while the other members solve as before (forced counts, 1e-9)."""
+    ws = bodies()[:3]
+    ws.insert(1, empty_body(21))
+    sims, states, batch, ores, gres = run_batch(ws, 4, frames=2, force_from_oracle=True,
+                                                matrix_free=mf, smoother=smoother)
+    for k, (w, (pos, vel)) in enumerate(zip(ws, states)):
+        if w.n_rows == 0:
+            assert (gres[-1][k]["pcg_iters"] == 0).all()
+            assert np.array_equal(batch.bodies[k].positions(), pos)
+            assert np.array_equal(batch.bodies[k].velocities(), vel)
+            log("empty member %d: Euler step bit-exact" % k)
+            continue
+        assert (gres[-1][k]["pcg_iters"] == ores[-1][k]["pcg_iters"]).all()
+        err = rel_pos_err(batch.bodies[k].positions(), pos)
+        log("member %d (%s, mf %d, smoother %d): pos err %.3e" % (k, w.name, mf, smoother, err))
+        assert err <= 1e-9
+    batch.close()
+
+
+def test_batch_of_bodies_without_constraints():
+    ws = [empty_body(22), empty_body(23)]
+    sims, states, batch, ores, gres = run_batch(ws, 3, frames=2)
+    for k, (pos, vel) in enumerate(states):
+        assert np.array_equal(batch.bodies[k].positions(), pos)
+        assert np.array_equal(batch.bodies[k].velocities(), vel)
+    batch.close()
