@@ -137,6 +137,25 @@ def _dev(t, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _vec(t, dtype, n, what):
+    """_dev plus a length check: the library reads and writes exactly n
+    entries through the pointer and cannot see the tensor's size."""
+    p = _dev(t, dtype)
+    if t.numel() != n:
+        raise ValueError("%s has %d entries, expected %d" % (what, t.numel(), n))
+    return p
+
+
+# vertex counts of the contexts and batches created here, for the length
+# checks of the calls that take per-vertex device arrays
+_NV = {}
+_BATCH_NV = {}
+
+
+def _key(h):
+    return h.value if isinstance(h, C.c_void_p) else int(h)
+
+
 def _check(ctx, st):
     if st != OK:
         msg = lib().mgpbd_last_error(ctx) if ctx else b""
@@ -191,6 +210,7 @@ def mgpbd_create(rest, inv_mass, tets, edges, vol_tet, compliance, dt, gravity,
                             _np_ptr(grav), C.byref(opt) if opt is not None else None, C.byref(h))
     if st != OK:
         raise MgpbdError(st, "mgpbd_create")
+    _NV[_key(h)] = rest.shape[0]
     return h
 
 
@@ -209,6 +229,9 @@ def mgpbd_setup(ctx, max_levels: int, reuse_interval: int):
 def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
     import torch
     f64 = torch.float64
+    nv = _NV.get(_key(ctx), x.numel())
+    for t, what in zip((x, y, z, vx, vy, vz), ("x", "y", "z", "vx", "vy", "vz")):
+        _vec(t, f64, nv, what)
     n = max(int(n_iters), 1)
     bn = np.zeros(n)
     its = np.zeros(n, np.int32)
@@ -229,6 +252,12 @@ def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
 
 def mgpbd_solve(ctx, rowptr, col, val, b, tol, x_out):
     import torch
+    n = rowptr.numel() - 1
+    if n < 0:
+        raise ValueError("rowptr must hold n + 1 entries")
+    _vec(val, torch.float64, col.numel(), "val")
+    _vec(b, torch.float64, n, "b")
+    _vec(x_out, torch.float64, n, "x_out")
     csr = Csr(rowptr.numel() - 1, col.numel(), _dev(rowptr, torch.int64).value,
               _dev(col, torch.int32).value, _dev(val, torch.float64).value)
     st = SolveStats()
@@ -243,6 +272,7 @@ def mgpbd_solve(ctx, rowptr, col, val, b, tol, x_out):
 
 def mgpbd_destroy(ctx):
     if ctx:
+        _NV.pop(_key(ctx), None)
         lib().mgpbd_destroy(ctx)
 
 
@@ -305,8 +335,14 @@ def mgpbd_get_matrix(ctx, l):
 def mgpbd_apply(ctx, x, y):
     """y = A x (device FP64 tensors of the context's row count), enqueued on
     the context's stream."""
-    assert x.dtype == y.dtype and x.is_cuda and y.is_cuda and x.numel() == y.numel()
-    _check(ctx, lib().mgpbd_apply(ctx, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+    import torch
+    m, _ = mgpbd_num_rows(ctx)
+    if m > 0:   # with no rows the library touches neither array (or reports E_STATE)
+        px = _vec(x, torch.float64, m, "x")
+        py = _vec(y, torch.float64, m, "y")
+    else:
+        px, py = _dev(x, torch.float64), _dev(y, torch.float64)
+    _check(ctx, lib().mgpbd_apply(ctx, px, py))
 
 
 def mgpbd_get_qr(ctx, l, n, n_agg, n_mem, K):
@@ -340,6 +376,7 @@ def mgpbd_get_colors(ctx, m):
 
 def mgpbd_selftest_sqrt_div(a, b):
     import torch
+    _vec(b, torch.float64, a.numel(), "b")
     s = torch.empty_like(a)
     q = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -357,6 +394,7 @@ def mgpbd_batch_create(ctxs):
     if st != OK:
         msg = lib().mgpbd_last_error(arr[0]) if len(ctxs) and arr[0] else b""
         raise MgpbdError(st, "mgpbd_batch_create: " + (msg or b"").decode())
+    _BATCH_NV[_key(h)] = [_NV.get(_key(c)) for c in ctxs]
     return h
 
 
@@ -368,12 +406,16 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
     """One frame for every body of the batch; returns one stats dict per body."""
     import torch
     nb = len(xyz_list)
+    sizes = _BATCH_NV.get(_key(batch))
+    if len(vxyz_list) != nb or (sizes is not None and len(sizes) != nb):
+        raise ValueError("expected positions and velocities for every body of the batch")
     xs = (C.c_void_p * (3 * nb))()
     vs = (C.c_void_p * (3 * nb))()
     for k, (p, v) in enumerate(zip(xyz_list, vxyz_list)):
+        nv = sizes[k] if sizes is not None and sizes[k] is not None else p[0].numel()
         for d in range(3):
-            xs[3 * k + d] = _dev(p[d], torch.float64).value
-            vs[3 * k + d] = _dev(v[d], torch.float64).value
+            xs[3 * k + d] = _vec(p[d], torch.float64, nv, "body %d position" % k).value
+            vs[3 * k + d] = _vec(v[d], torch.float64, nv, "body %d velocity" % k).value
     n = max(int(n_iters), 1)
     arrs = [dict(bnorm=np.zeros(n), pcg_iters=np.zeros(n, np.int32), pcg_ratio=np.zeros(n),
                  setup_ran=np.zeros(n, np.int32)) for _ in range(nb)]
@@ -399,6 +441,7 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
 
 def mgpbd_batch_destroy(batch):
     if batch:
+        _BATCH_NV.pop(_key(batch), None)
         lib().mgpbd_batch_destroy(batch)
 
 

@@ -61,3 +61,16 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.mgpbd_last_error(None) == b"null context"
     assert lib.mgpbd_apply(None, None, None) == binding.E_INVALID_ARG
     assert lib.mgpbd_get_qr(None, 0, None, None, None, None) == binding.E_INVALID_ARG
+
+
+def test_binding_rejects_host_and_short_tensors_before_calling_the_library():
+    """The C ABI takes bare device pointers, so the binding checks device,
+    dtype, contiguity and length itself; here on host tensors (no GPU)."""
+    torch = pytest.importorskip("torch")
+    from paper_2505_13390_amd import binding
+    with pytest.raises(TypeError):
+        binding._dev(torch.zeros(4, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        binding._vec(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "x")
+    with pytest.raises(TypeError):
+        binding._dev([0.0, 1.0])
