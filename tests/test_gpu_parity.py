@@ -424,3 +424,30 @@ def test_body_without_constraints_is_a_plain_euler_step():
     assert np.array_equal(body.positions(), pos)
     assert np.array_equal(body.velocities(), vel)
     body.close()
+
+
+def test_frame_with_zero_iterations_then_lazy_frames():
+    """n_iters = 0: the frame is the predict and velocity steps of Algorithm 1
+    alone (bit-exact with the oracle) and counts as a frame; the next frames
+    set up lazily on the same schedule as the oracle and match it."""
+    w = W.beam_c0()
+    oo, go = opts()
+    sim = O.Sim(w, oo)
+    pos, vel = O.positions(w)
+    body = B.Body(w, go)
+    ro = sim.step(pos, vel, 0)
+    rg = body.step(0)
+    assert ro["status"] == 0 and rg["iters_done"] == 0
+    assert np.array_equal(body.positions(), pos)
+    assert np.array_equal(body.velocities(), vel)
+    for f in range(2):
+        ro = sim.step(pos, vel, 4)
+        assert ro["status"] == 0
+        B.mgpbd_force_pcg_iters(body.ctx, ro["pcg_iters"])
+        rg = body.step(4)
+        assert (rg["setup_ran"] == ro["setup"]).all(), (rg["setup_ran"], ro["setup"])
+        err = rel_pos_err(body.positions(), pos)
+        log("frame %d after an empty frame: setup %s position err %.3e"
+            % (f + 1, rg["setup_ran"].tolist(), err))
+        assert err <= 1e-9
+    body.close()
