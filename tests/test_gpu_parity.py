@@ -451,3 +451,38 @@ def test_frame_with_zero_iterations_then_lazy_frames():
             % (f + 1, rg["setup_ran"].tolist(), err))
         assert err <= 1e-9
     body.close()
+
+
+def test_fully_pinned_bodies():
+    """Every vertex pinned (inverse mass 0): with compliant rows A is the
+    diagonal of compliances, b = 0 and nothing moves, as in the oracle (bit
+    for bit); with rigid rows (compliance 0) A is the zero matrix and both
+    sides report the same breakdown status."""
+    w = W.tiny_beam(3, 1, 1)
+    w.inv_mass = np.zeros_like(w.inv_mass)
+    oo, go = opts()
+    sim = O.Sim(w, oo)
+    pos, vel = O.positions(w)
+    ro = sim.step(pos, vel, 2)
+    assert ro["status"] == 0
+    body = B.Body(w, go)
+    rg = body.step(2)
+    assert np.array_equal(body.positions(), pos)
+    assert np.array_equal(body.velocities(), vel)
+    assert (rg["pcg_iters"] == 0).all() and (rg["bnorm"] == 0).all()
+    rp, col, val = B.mgpbd_get_matrix(body.ctx, 0)
+    body.close()
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    assert (val[rows != col] == 0).all()
+    assert (val[rows == col] > 0).all()
+    w.alpha = np.zeros_like(w.alpha)
+    sim = O.Sim(w, oo)
+    pos, vel = O.positions(w)
+    ro = sim.step(pos, vel, 2)
+    assert ro["status"] == B.E_BREAKDOWN
+    body = B.Body(w, go)
+    with pytest.raises(B.MgpbdError) as e:
+        body.step(2)
+    log("rigid fully pinned body: oracle status %d, library %s" % (ro["status"], e.value))
+    assert e.value.status == B.E_BREAKDOWN
+    body.close()
