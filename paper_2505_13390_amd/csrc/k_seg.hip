@@ -74,10 +74,28 @@ __device__ void seg_total(const SegTab &t, const double *partials, int seg, doub
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   const int b0 = t.first[seg], b1 = t.first[seg + 1];
+  const int bd = blockDim.x;
+  // eight independent loads per value and round, summed in a fixed order
+  double acc[NV][8];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[k][u] = 0.0;
+  int q = b0 + threadIdx.x;
+  for (; q + 7 * bd < b1; q += 8 * bd) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[k][u] += partials[(size_t)k * t.nblk + q + u * bd];
+  }
+  for (; q < b1; q += bd) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k][0] += partials[(size_t)k * t.nblk + q];
+  }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int q = b0 + threadIdx.x; q < b1; q += blockDim.x) s += partials[(size_t)k * t.nblk + q];
+    double s = ((acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3])) +
+               ((acc[k][4] + acc[k][5]) + (acc[k][6] + acc[k][7]));
     s = group_sum<kWave>(s);
     if (lane == 0) sh[k][w] = s;
   }
