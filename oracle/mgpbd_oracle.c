@@ -31,7 +31,8 @@
  *    PCG with one V-cycle as preconditioner.
  *  - Sec. 4.5: omega-Jacobi smoother, 2 pre + 2 post sweeps,
  *    omega = 2 / (lambda_max(D^-1 A) + lambda_min), lambda_max by the power
- *    method, lambda_min a user estimate (0.1); computed at setup only.
+ *    method (run until its eigen-residual is small, power_lmax), lambda_min a
+ *    user estimate (0.1); computed at setup only.
  *    Optionally the Chebyshev smoother of the same subsection: s steps of
  *    Chebyshev acceleration of Jacobi on the interval [lambda_min, lambda_max]
  *    (the recurrence of Saad, Iterative Methods for Sparse Linear Systems,
@@ -40,7 +41,7 @@
  *    a greedy colouring in descending priority, forward colour order before
  *    the coarse correction and reversed order after it (the adjoint, so the
  *    V-cycle stays symmetric).
- *  - Sec. 6 (As-Rigid-As-Possible constraints): a tet row with
+ *  - Sec. 5.3, Eq. 8 (As-Rigid-As-Possible constraints): a tet row with
  *    C = |F - R|_F^2, F the deformation gradient and R its nearest rotation
  *    (arap_eval, with the readings listed there).
  *
@@ -82,7 +83,7 @@ typedef struct orc_opts {
   int coarse_max;      /* stop coarsening at <= this many rows (Sec. 4.1): 400 */
   int dense_max;       /* largest coarsest level accepted for dense Cholesky: 4096 */
   int max_levels;      /* cap on the number of levels: 16 */
-  int power_iters;     /* power-method iterations for lambda_max: 30 */
+  int power_iters;     /* power-method steps before the first stopping test: 30 */
   double omega_relax;  /* x += omega dx (Algorithm 1): 0.1 */
   double tol;          /* PCG relative residual: 1e-6 */
   int max_pcg;         /* PCG iteration cap: 5000 */
@@ -94,6 +95,8 @@ typedef struct orc_opts {
   double lmax_scale;   /* omega = 2 / (lmax_scale * lambda_max + lambda_min): 1.05 */
   int smoother;        /* 0 = omega-Jacobi, 1 = Chebyshev, 2 = multicolour GS (Sec. 4.5): 0 */
   int n_cand;          /* near-kernel candidates per level K (Sec. 4.3 uses six): 1 */
+  int power_max;       /* power-method step cap: 500 */
+  double power_tol;    /* power-method stop: eigen-residual <= power_tol * estimate: 1e-2 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -117,6 +120,8 @@ void orc_default_opts(orc_opts *o) {
   o->lmax_scale = 1.05;
   o->smoother = 0;
   o->n_cand = 1;
+  o->power_max = 500;
+  o->power_tol = 1e-2;
 }
 
 /* ------------------------------------------------------------------ */
@@ -212,7 +217,7 @@ typedef struct {
 } orc_sim;
 
 /* ------------------------------------------------------------------ */
-/* ARAP constraint (Sec. 6, As-Rigid-As-Possible Constraints)          */
+/* ARAP constraint (Sec. 5.3, Eq. 8, As-Rigid-As-Possible Constraints)          */
 /* ------------------------------------------------------------------ */
 /* Per tet (x0, x1, x2, x3): Ds = [x1 - x0, x2 - x0, x3 - x0] (columns),
    Dm the same matrix at rest, F = Ds Dm^-1 the deformation gradient and
@@ -993,24 +998,43 @@ static void galerkin_values(const csr *a, const level_t *lv, int K, csr *c) {
       if (c->col[k] < q) c->val[k] = c->val[find_col(c, c->col[k], (int32_t)q)];
 }
 
-/* lambda_max(D^-1 A) by the power method, Rayleigh quotient v^T A v / v^T D v */
-static double power_lmax(const csr *a, const double *diag, int iters, uint64_t seed, int level) {
+/* lambda_max(D^-1 A) by the power method (Sec. 4.5) with a stopping test.
+   v <- D^-1 A v / |D^-1 A v| from a positive pseudo-random start (stream 5).
+   At step k = power_iters and then every POWER_CHECK steps, with w = A v_k:
+   theta = v^T A v / v^T D v (the Rayleigh quotient), u = D^-1 w - theta v
+   (the eigen-residual), and the method stops once
+   |u|_D <= power_tol * theta * |v|_D, or at step power_max, returning theta.
+   |x|_D = sqrt(x^T D x): D^-1 A is self-adjoint in that inner product, so a
+   small residual means v is close to an eigenvector. */
+#define POWER_CHECK 10
+static double power_lmax(const csr *a, const double *diag, const orc_opts *o, int level) {
   int64_t n = a->n;
   double *v = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
-  for (int64_t i = 0; i < n; ++i) v[i] = uniform01(seed, 5, ((uint64_t)level << 40) + (uint64_t)i);
-  for (int it = 0; it < iters; ++it) {
+  for (int64_t i = 0; i < n; ++i)
+    v[i] = uniform01(o->seed, 5, ((uint64_t)level << 40) + (uint64_t)i);
+  double theta = 0.0;
+  for (int it = 0;; ++it) {
     spmv(a, v, w);
+    int last = it >= o->power_max;
+    if (last || (it >= o->power_iters && (it - o->power_iters) % POWER_CHECK == 0)) {
+      double num = dot(n, v, w);
+      double den = 0.0;
+      for (int64_t i = 0; i < n; ++i) den += v[i] * diag[i] * v[i];
+      theta = num / den;
+      double res = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        double u = w[i] / diag[i] - theta * v[i];
+        res += u * diag[i] * u;
+      }
+      if (last || sqrt(res) <= o->power_tol * theta * sqrt(den)) break;
+    }
     for (int64_t i = 0; i < n; ++i) w[i] = w[i] / diag[i];
     double nrm = sqrt(dot(n, w, w));
     if (!(nrm > 0.0)) break;
     for (int64_t i = 0; i < n; ++i) v[i] = w[i] / nrm;
   }
-  spmv(a, v, w);
-  double num = dot(n, v, w);
-  double den = 0.0;
-  for (int64_t i = 0; i < n; ++i) den += v[i] * diag[i] * v[i];
   free(v); free(w);
-  return num / den;
+  return theta;
 }
 
 static int dense_cholesky(hier_t *h) {
@@ -1085,8 +1109,7 @@ static int finish_level(hier_t *h, int l) {
     lv->diag[i] = csr_get_diag(&lv->A, i);
     if (!(lv->diag[i] > 0.0)) return ORC_E_BREAKDOWN;
   }
-  lv->lmax = nl ? h->o.lmax_scale * power_lmax(&lv->A, lv->diag, h->o.power_iters, h->o.seed, l)
-               : 0.0;
+  lv->lmax = nl ? h->o.lmax_scale * power_lmax(&lv->A, lv->diag, &h->o, l) : 0.0;
   lv->omega = nl ? 2.0 / (lv->lmax + h->o.lambda_min) : 0.0;
   if (h->o.smoother == 2) {
     /* rows of each colour in ascending order (greedy colouring in
@@ -1161,7 +1184,8 @@ hier_t *orc_hier_build(int64_t n, const int64_t *rowptr, const int32_t *col, con
   if (!h) { *status = ORC_E_NOMEM; return NULL; }
   if (opts) h->o = *opts; else orc_default_opts(&h->o);
   const orc_opts *o = &h->o;
-  if (o->max_levels < 1 || o->max_levels > 32 || o->n_cand < 1 || o->n_cand > 8) {
+  if (o->max_levels < 1 || o->max_levels > 32 || o->n_cand < 1 || o->n_cand > 8 ||
+      o->power_iters < 0 || o->power_max < 0 || !(o->power_tol >= 0.0)) {
     *status = ORC_E_INVALID; free(h); return NULL;
   }
   for (int64_t i = 0; i < n; ++i)
@@ -1462,6 +1486,14 @@ int orc_hier_level_qr(const hier_t *h, int l, int32_t *kq, int64_t *coff, double
   if (coff) memcpy(coff, lv->coff, sizeof(int64_t) * (lv->n_agg + 1));
   if (Q) memcpy(Q, lv->Q, sizeof(double) * lv->agg_ptr[lv->n_agg] * K);
   if (B) memcpy(B, lv->B, sizeof(double) * lv->A.n * K);
+  return ORC_OK;
+}
+
+/* z = A_L^-1 r with the last level's dense Cholesky factor (a test hook; the
+   V-cycle applies the same solve at the last level) */
+int orc_hier_coarse_solve(const hier_t *h, const double *r, double *z) {
+  if (!h->last_dense) return ORC_E_INVALID;
+  chol_solve(h, r, z);
   return ORC_OK;
 }
 

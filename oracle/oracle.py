@@ -34,7 +34,8 @@ class Opts(C.Structure):
                 ("omega_relax", C.c_double), ("tol", C.c_double), ("max_pcg", C.c_int),
                 ("seed", C.c_uint64), ("reuse_interval", C.c_int), ("b_mode", C.c_int),
                 ("eps_b", C.c_double), ("flexible", C.c_int), ("lmax_scale", C.c_double),
-                ("smoother", C.c_int), ("n_cand", C.c_int)]
+                ("smoother", C.c_int), ("n_cand", C.c_int), ("power_max", C.c_int),
+                ("power_tol", C.c_double)]
 
 
 _lib = None
@@ -92,6 +93,8 @@ def lib():
         L.orc_hier_level_transfer.argtypes = [P, C.c_int, P, P, P]
         L.orc_hier_level_qr.restype = C.c_int
         L.orc_hier_level_qr.argtypes = [P, C.c_int, P, P, P, P]
+        L.orc_hier_coarse_solve.restype = C.c_int
+        L.orc_hier_coarse_solve.argtypes = [P, P, P]
         L.orc_hier_colors.restype = C.c_int
         L.orc_hier_colors.argtypes = [P, P]
         L.orc_pcg.restype = C.c_int
@@ -213,6 +216,15 @@ class Hier:
         st = lib().orc_hier_refresh(self.h, _p(val0))
         if st != OK:
             raise OracleError(st, "refresh")
+
+    def coarse_solve(self, r):
+        """z = A_L^-1 r with the last level's dense factor."""
+        r = np.ascontiguousarray(r, np.float64)
+        z = np.zeros_like(r)
+        st = lib().orc_hier_coarse_solve(self.h, _p(r), _p(z))
+        if st != OK:
+            raise OracleError(st, "coarse_solve")
+        return z
 
     def vcycle(self, r):
         r = np.ascontiguousarray(r, np.float64)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's ARAP constraint (Sec. 6, As-Rigid-As-Possible
+"""Pins of the oracle's ARAP constraint (Sec. 5.3, Eq. 8, As-Rigid-As-Possible
 constraints): C = |F - R|_F^2 per tet, F the deformation gradient, R its
 nearest rotation. Each check rests on something other than the oracle: a
 library polar decomposition or SVD, closed forms, invariances, brute-force
