@@ -61,7 +61,8 @@ typedef struct {
   int32_t coarse_max;   /* coarsen until a level has at most this many rows (Sec. 4.1): 400 */
   int32_t dense_max;    /* largest last level accepted for the dense Cholesky solve: 4096 */
   int32_t max_levels;   /* cap on the number of levels (1..32): 16 */
-  int32_t power_iters;  /* power-method iterations for lambda_max (Sec. 4.5): 30 */
+  int32_t power_iters;  /* power-method steps for lambda_max (Sec. 4.5) before its first
+                           stopping test (see power_tol): 30 */
   double omega_relax;   /* relaxation of x += omega dx (Algorithm 1 and Sec. 4): 0.1 */
   double tol;           /* PCG stop: |r| <= tol |b| (recurrence residual): 1e-6 */
   int32_t max_pcg;      /* PCG iteration cap per solve: 5000 */
@@ -102,6 +103,12 @@ typedef struct {
                            most 1e-8 of their norm, so an aggregate has 1..K coarse
                            unknowns; P takes the Q blocks and the next level's
                            candidates the R rows. 1 = one normalised candidate: 1 */
+  int32_t power_max;    /* power-method step cap: 500 */
+  double power_tol;     /* power-method stop, tested at step power_iters and every 10 steps
+                           after it: with theta = v^T A v / v^T D v, stop once
+                           |D^-1 A v - theta v|_D <= power_tol * theta * |v|_D
+                           (|x|_D = sqrt(x^T D x)) or at step power_max; lambda_max =
+                           theta. power_max = power_iters gives a fixed count: 1e-2 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.
@@ -119,7 +126,7 @@ typedef struct {
    n_vols volume constraints, then the n_arap ARAP constraints. edges:
    [n_edges][2], i < j, strictly ascending lexicographic; vol_tet and
    arap_tet: indices into mesh tets. All arrays host.
-   An ARAP row (Sec. 6, As-Rigid-As-Possible constraints) is
+   An ARAP row (Sec. 5.3, Eq. 8, As-Rigid-As-Possible constraints) is
    C = |F - R|_F^2 for its tet, F = Ds Dm^-1 the deformation gradient
    (Ds = [x1 - x0, x2 - x0, x3 - x0], Dm the same at rest) and R the rotation
    (det +1) nearest to F; target C = 0. The paper takes its compliance as
@@ -204,14 +211,20 @@ mgpbd_status mgpbd_setup(mgpbd_ctx *ctx, int32_t max_levels, int32_t reuse_inter
    coarse operators, MGPCG, dx = M^-1 gradC^T dlambda of Eq. 5, lambda +=
    dlambda, x += omega dx), then v = (x - x_old) / dt. PCG non-convergence
    is not an error (counted in stats). Errors: E_INVALID_ARG for non-finite
-   positions (state unchanged), E_BREAKDOWN, E_SETUP, E_STATE without a mesh. */
+   positions, E_BREAKDOWN, E_SETUP, E_DEVICE, E_STATE without a mesh. On every
+   error x, y, z, vx, vy, vz hold what they held on entry, the frame counter
+   does not advance, lambda is undefined until the next successful step, and
+   the next step rebuilds the hierarchy. */
 mgpbd_status mgpbd_step(mgpbd_ctx *ctx, double *x, double *y, double *z, double *vx,
                         double *vy, double *vz, int32_t n_iters, mgpbd_step_stats *st);
 
 /* Solve A x = b for a caller matrix (device CSR, see mgpbd_csr; b and x_out
    device [n]) with a fresh setup on A and MGPCG to tol (Sec. 4.4). The
    hierarchy stays inspectable afterwards. Returns E_NOT_CONVERGED (x_out
-   still written) when max_pcg is reached. */
+   still written) when max_pcg is reached. The structure of A is checked on the
+   device before use: E_INVALID_ARG (nothing else read) unless rowptr[0] = 0,
+   rowptr is non-decreasing with rowptr[n] = nnz, and every row's columns lie
+   in [0, n) and ascend strictly. */
 mgpbd_status mgpbd_solve(mgpbd_ctx *ctx, const mgpbd_csr *A, const double *b, double tol,
                          double *x_out, mgpbd_solve_stats *st);
 
@@ -287,7 +300,9 @@ mgpbd_status mgpbd_batch_create(mgpbd_ctx *const *ctxs, int32_t n, mgpbd_batch *
    with mgpbd_force_pcg_iters on a member context apply to that body. A body
    whose |b| falls below eps_b stops iterating (zero right-hand side
    afterwards). The lazy-setup schedule follows the batch's own frame count;
-   mgpbd_setup on the batch context changes it. */
+   mgpbd_setup on the batch context changes it. Errors as for mgpbd_step: on
+   every error the bodies' arrays hold what they held on entry (the batch
+   steps copies of them and writes back only after a successful frame). */
 mgpbd_status mgpbd_batch_step(mgpbd_batch *b, double *const *xyz, double *const *vxyz,
                               int32_t n_iters, mgpbd_step_stats *st);
 /* The batch's system context, for mgpbd_setup, mgpbd_set_stream and the

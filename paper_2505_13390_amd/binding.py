@@ -30,7 +30,8 @@ class Options(C.Structure):
                 ("lmax_scale", C.c_double), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("profile_spmv", C.c_int32),
                 ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32),
-                ("matrix_free", C.c_int32), ("smoother", C.c_int32), ("n_cand", C.c_int32)]
+                ("matrix_free", C.c_int32), ("smoother", C.c_int32), ("n_cand", C.c_int32),
+                ("power_max", C.c_int32), ("power_tol", C.c_double)]
 
 
 class Mesh(C.Structure):

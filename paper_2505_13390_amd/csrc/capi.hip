@@ -42,7 +42,7 @@ struct mgpbd_ctx {
   DevBuf<int64_t> vptr;
   DevBuf<int32_t> vrow;
   DevBuf<int8_t> vslot;
-  DevBuf<double> w, alpha_t, rest_c, C, grad, lambda, b, old[3];
+  DevBuf<double> w, alpha_t, rest_c, C, grad, lambda, b, old[3], vold[3];
   DevBuf<int> bad;
   // ARAP rows (absent without them): kind[r] = 1 marks one, dm_inv[r] holds
   // the inverse rest shape matrix of its tet
@@ -100,8 +100,9 @@ void check_options(const mgpbd_options &o) {
   MG_REQUIRE(o.coarse_max >= 0 && o.dense_max >= 0 && o.dense_max <= 8192, MGPBD_E_INVALID_ARG,
              "coarse_max / dense_max");
   MG_REQUIRE(o.max_levels >= 1 && o.max_levels <= 32, MGPBD_E_INVALID_ARG, "max_levels");
-  MG_REQUIRE(o.power_iters >= 0 && o.max_pcg >= 1 && o.check_every >= 1, MGPBD_E_INVALID_ARG,
-             "iteration counts");
+  MG_REQUIRE(o.power_iters >= 0 && o.power_max >= 0 && o.max_pcg >= 1 && o.check_every >= 1,
+             MGPBD_E_INVALID_ARG, "iteration counts");
+  MG_REQUIRE(o.power_tol >= 0.0 && std::isfinite(o.power_tol), MGPBD_E_INVALID_ARG, "power_tol");
   MG_REQUIRE(o.tol >= 0.0 && o.lmax_scale > 0.0, MGPBD_E_INVALID_ARG, "tol / lmax_scale");
   MG_REQUIRE(o.precision == MGPBD_PREC_FP64 || o.precision == MGPBD_PREC_MIXED,
              MGPBD_E_INVALID_ARG, "precision");
@@ -146,7 +147,10 @@ void alloc_state(mgpbd_ctx *c) {
   c->lambda.alloc(c->m);
   c->b.alloc(c->m);
   c->bad.alloc(1);
-  for (int k = 0; k < 3; ++k) c->old[k].alloc(c->nv);
+  for (int k = 0; k < 3; ++k) {
+    c->old[k].alloc(c->nv);
+    c->vold[k].alloc(c->nv);
+  }
   S.mf = MfView<double>();
   S.mf32 = MfView<float>();
   if (c->opt.matrix_free && c->m > 0) {
@@ -186,6 +190,10 @@ void alloc_state(mgpbd_ctx *c) {
   }
 }
 
+void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_iters,
+               const std::vector<const std::vector<int32_t> *> &force,
+               mgpbd_step_stats *stats);
+
 // One frame of Algorithm 1 for every body of c. force[k] (nullable) fixes
 // body k's PCG iteration counts; stats (nullable) holds one struct per body.
 // A body whose |b| falls below eps_b stops: later iterations solve a zero
@@ -193,10 +201,7 @@ void alloc_state(mgpbd_ctx *c) {
 void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_iters,
               const std::vector<const std::vector<int32_t> *> &force, mgpbd_step_stats *stats) {
   hipStream_t st = c->st;
-  Solver &S = *c->solver;
-  const int nb = c->nb;
-  const int64_t nv = c->nv, m = c->m;
-  double *oxyz[3] = {c->old[0].p, c->old[1].p, c->old[2].p};
+  const int64_t nv = c->nv;
   MG_HIP(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
   for (int k = 0; k < 3; ++k) {
     launch_check_finite(nv, xyz[k], c->bad.p, st);
@@ -206,6 +211,42 @@ void run_step(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_i
   MG_HIP(hipMemcpyAsync(&hbad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
   MG_REQUIRE(hbad == 0, MGPBD_E_INVALID_ARG, "non-finite positions or velocities");
+  // the velocities entering the frame, so that a failed frame can hand the
+  // caller back its own state (the positions are kept by the predict)
+  for (int k = 0; k < 3; ++k)
+    if (nv)
+      MG_HIP(hipMemcpyAsync(c->vold[k].p, vxyz[k], sizeof(double) * nv, hipMemcpyDeviceToDevice,
+                            st));
+  try {
+    run_frame(c, xyz, vxyz, n_iters, force, stats);
+  } catch (...) {
+    // an error inside the frame (breakdown, failed setup, device error):
+    // restore x and v as they entered, drop the partial frame and make the
+    // next step rebuild the hierarchy
+    for (int k = 0; k < 3; ++k)
+      if (nv) {
+        (void)hipMemcpyAsync(xyz[k], c->old[k].p, sizeof(double) * nv, hipMemcpyDeviceToDevice,
+                             st);
+        (void)hipMemcpyAsync(vxyz[k], c->vold[k].p, sizeof(double) * nv,
+                             hipMemcpyDeviceToDevice, st);
+      }
+    (void)hipStreamSynchronize(st);
+    c->stale = true;
+    throw;
+  }
+}
+
+// The frame itself (after the finiteness check): predict, global iterations,
+// velocity. Throws on breakdown or setup failure with x and v part-updated;
+// run_step restores them.
+void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_iters,
+               const std::vector<const std::vector<int32_t> *> &force,
+               mgpbd_step_stats *stats) {
+  hipStream_t st = c->st;
+  Solver &S = *c->solver;
+  const int nb = c->nb;
+  const int64_t nv = c->nv, m = c->m;
+  double *oxyz[3] = {c->old[0].p, c->old[1].p, c->old[2].p};
   Timer total, part;
   total.start(st);
   double ms_setup = 0.0, ms_pcg = 0.0;
@@ -345,6 +386,8 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->matrix_free = 1;
   o->smoother = 0;
   o->n_cand = 1;
+  o->power_max = 500;
+  o->power_tol = 1e-2;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {
@@ -527,6 +570,16 @@ mgpbd_status mgpbd_solve(mgpbd_ctx *c, const mgpbd_csr *A, const double *b, doub
     MG_HIP(hipMemcpyAsync(&last, A->rowptr + A->n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     MG_HIP(hipStreamSynchronize(st));
     MG_REQUIRE(last == A->nnz, MGPBD_E_INVALID_ARG, "rowptr[n] != nnz");
+    // every row's bounds and columns, before any kernel indexes through them
+    c->bad.alloc(1);
+    MG_HIP(hipMemsetAsync(c->bad.p, 0, sizeof(int), st));
+    launch_validate_csr(A->n, A->nnz, A->rowptr, A->col, c->bad.p, st);
+    int hbad = 0;
+    MG_HIP(hipMemcpyAsync(&hbad, c->bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    MG_REQUIRE(hbad == 0, MGPBD_E_INVALID_ARG,
+               "malformed CSR: row bounds not monotone in [0, nnz] or a column outside [0, n) "
+               "or not strictly ascending");
     Level &F = S.L0();
     F.n = A->n;
     F.nnz = A->nnz;

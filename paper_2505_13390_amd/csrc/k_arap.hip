@@ -1,4 +1,4 @@
-// ARAP constraint rows (Sec. 6, As-Rigid-As-Possible constraints): per tet
+// ARAP constraint rows (Sec. 5.3, Eq. 8, As-Rigid-As-Possible constraints): per tet
 // (x0, x1, x2, x3), F = Ds Dm^-1 with Ds = [x1 - x0, x2 - x0, x3 - x0] and
 // Dm the same matrix at rest, C = |F - R|_F^2 with R the rotation nearest
 // to F (det R = +1; an inverted tet keeps C > 0), and the gradient

@@ -396,18 +396,29 @@ __global__ __launch_bounds__(kBlock) void k_s_rayleigh(SegTab t, const double *_
                                                        const double *__restrict__ diag,
                                                        double *partials) {
   SEG_BLOCK(t);
-  double s2[2] = {0.0, 0.0};
+  double s3[3] = {0.0, 0.0, 0.0};
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double vi = v[i];
-    s2[0] += vi * Av[i];
-    s2[1] += vi * diag[i] * vi;
+    const double vi = v[i], ai = Av[i], di = diag[i];
+    s3[0] += vi * ai;
+    s3[1] += vi * di * vi;
+    s3[2] += ai * (ai / di);
   }
-  seg_partials<2>(s2, partials);
+  seg_partials<3>(s3, partials);
+}
+__global__ __launch_bounds__(kBlock) void k_s_fin_store3(SegTab t, const double *partials,
+                                                         double *out) {
+  double tot[3];
+  seg_total<3>(t, partials, blockIdx.x, tot);
+  if (threadIdx.x == 0) {
+    out[3 * blockIdx.x] = tot[0];
+    out[3 * blockIdx.x + 1] = tot[1];
+    out[3 * blockIdx.x + 2] = tot[2];
+  }
 }
 void launch_s_rayleigh(const SegTab &t, const double *v, const double *Av, const double *diag,
                        double *out, double *partials, hipStream_t s) {
   k_s_rayleigh<<<t.nblk, kBlock, 0, s>>>(t, v, Av, diag, partials);
-  k_s_fin_store2<<<t.nseg, kBlock, 0, s>>>(t, partials, out);
+  k_s_fin_store3<<<t.nseg, kBlock, 0, s>>>(t, partials, out);
 }
 __global__ void k_s_pow_init(SegTab t, uint64_t salt, int level, double *__restrict__ v) {
   SEG_BLOCK(t);

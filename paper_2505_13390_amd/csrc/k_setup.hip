@@ -29,6 +29,32 @@ namespace mgpbd {
   }
 
 // ------------------------------------------------------------ diagonal
+// Structure check of a caller CSR before any kernel indexes through it: each
+// row's bounds must satisfy 0 = rp[0] <= rp[i] <= rp[i+1] <= nnz and its
+// columns must lie in [0, n) and ascend strictly. A row whose bounds are bad
+// is flagged without reading its columns, so the check itself reads only
+// rp[0..n] and col[0..nnz).
+__global__ void k_validate_csr(int64_t n, int64_t nnz, const int64_t *__restrict__ rp,
+                               const int32_t *__restrict__ col, int *bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t lo = rp[i], hi = rp[i + 1];
+  bool ok = lo >= 0 && lo <= hi && hi <= nnz && (i > 0 || lo == 0);
+  if (ok) {
+    int64_t prev = -1;
+    for (int64_t e = lo; e < hi; ++e) {
+      const int64_t c = col[e];
+      if (c <= prev || c >= n) { ok = false; break; }
+      prev = c;
+    }
+  }
+  if (!ok) atomicExch(bad, 1);
+}
+void launch_validate_csr(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col, int *bad,
+                         hipStream_t s) {
+  if (n) k_validate_csr<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, nnz, rp, col, bad);
+}
+
 __global__ void k_diagpos(int64_t n, const int64_t *__restrict__ rp,
                           const int32_t *__restrict__ col, int64_t *__restrict__ dpos, int *bad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,35 +573,186 @@ void launch_normalize(int64_t na, const int64_t *ap, const int32_t *mem, const d
 }
 
 // ------------------------------------------------------------ Galerkin
-// One wavefront per coarse row a. An LDS open-addressing table holds the
-// distinct coarse columns b = agg(j) met in the rows of a's members.
+// One wavefront per coarse row a. An open-addressing table holds the
+// distinct coarse columns b = agg(j) met in the rows of a's members. The
+// table lives in LDS (kHashCap slots) for every row that fits; a row with
+// more distinct columns is redone with a table in global memory sized for
+// its entries (the *_big kernels), so no row is ever refused.
 constexpr int kHashCap = 1024;
+constexpr int kHashShift = 22;   // 32 - log2(kHashCap)
 
-__device__ __forceinline__ int hash_slot(int32_t b) {
-  return (int)(((uint32_t)b * 2654435761u) >> 22) & (kHashCap - 1);
+// the table of one row: cap slots (a power of two), shift = 32 - log2(cap)
+struct GalTab {
+  int32_t *keys;    // coarse column per slot (-1 = empty)
+  int32_t *rank;    // sorted position of the slot's column
+  int32_t *list;    // distinct columns, then sorted
+  int32_t *start;   // list offset of each rank (within the row)
+  int32_t *cursor;  // per-rank counts, then placement cursors
+  int cap, shift;
+};
+
+__device__ __forceinline__ int hash_slot(int32_t b, int shift, int cap) {
+  return (int)(((uint32_t)b * 2654435761u) >> shift) & (cap - 1);
 }
 // insert b; returns 1 if it was new, 0 if present, -1 if the table is full
-__device__ __forceinline__ int hash_insert(int32_t *keys, int32_t b) {
-  int s = hash_slot(b);
-  for (int probe = 0; probe < kHashCap; ++probe) {
+__device__ __forceinline__ int hash_insert(int32_t *keys, int shift, int cap, int32_t b) {
+  int s = hash_slot(b, shift, cap);
+  for (int probe = 0; probe < cap; ++probe) {
     int32_t old = atomicCAS(&keys[s], -1, b);
     if (old == -1) return 1;
     if (old == b) return 0;
-    s = (s + 1) & (kHashCap - 1);
+    s = (s + 1) & (cap - 1);
   }
   return -1;
 }
-__device__ __forceinline__ int hash_find(const int32_t *keys, int32_t b) {
-  int s = hash_slot(b);
-  for (int probe = 0; probe < kHashCap; ++probe) {
+__device__ __forceinline__ int hash_find(const int32_t *keys, int shift, int cap, int32_t b) {
+  int s = hash_slot(b, shift, cap);
+  for (int probe = 0; probe < cap; ++probe) {
     int32_t k = keys[s];
     if (k == b) return s;
     if (k == -1) return -1;
-    s = (s + 1) & (kHashCap - 1);
+    s = (s + 1) & (cap - 1);
   }
   return -1;
 }
 
+// distinct coarse columns (*nd) and connecting entries (*tot) of row a; full
+// when the table could not hold them
+__device__ void gal_count_row(int64_t a, const int64_t *__restrict__ ap,
+                              const int32_t *__restrict__ mem, const int64_t *__restrict__ rp,
+                              const int32_t *__restrict__ col, const int32_t *__restrict__ agg,
+                              const GalTab &T, int64_t *nd, int64_t *tot, int *full) {
+  const int lane = threadIdx.x;
+  for (int s = lane; s < T.cap; s += kWave) T.keys[s] = -1;
+  __syncthreads();
+  int64_t mytot = 0, mynew = 0;
+  int myfull = 0;
+  for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
+    int32_t i = mem[t];
+    for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+      int32_t b = agg[col[e]];
+      if (b < 0) continue;
+      ++mytot;
+      int r = hash_insert(T.keys, T.shift, T.cap, b);
+      if (r == 1) ++mynew;
+      else if (r < 0) myfull = 1;
+    }
+  }
+  *tot = group_sum<kWave>(mytot);
+  *nd = group_sum<kWave>(mynew);
+  *full = group_sum<kWave>(myfull);
+  __syncthreads();
+}
+
+// the sorted columns of row a, its Galerkin lists (fine entries per coarse
+// entry, ascending fine order); the table must hold the row
+__device__ void gal_fill_row(int64_t a, const int64_t *__restrict__ ap,
+                             const int32_t *__restrict__ mem, const int64_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, const int32_t *__restrict__ agg,
+                             const int64_t *__restrict__ crp, const int64_t *__restrict__ eoff,
+                             int32_t *__restrict__ ccol, int32_t *__restrict__ crow,
+                             int64_t *__restrict__ gl_ptr, int32_t *__restrict__ gl_idx,
+                             int32_t *__restrict__ gl_row, const GalTab &T) {
+  const int lane = threadIdx.x;
+  for (int s = lane; s < T.cap; s += kWave) { T.keys[s] = -1; T.cursor[s] = 0; T.start[s] = 0; }
+  __syncthreads();
+  for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
+    int32_t i = mem[t];
+    for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+      int32_t b = agg[col[e]];
+      if (b < 0) continue;
+      (void)hash_insert(T.keys, T.shift, T.cap, b);
+    }
+  }
+  __syncthreads();
+  // compact the occupied slots into list (order irrelevant: sorted next)
+  int n_d = 0;
+  for (int s0 = 0; s0 < T.cap; s0 += kWave) {
+    const int s = s0 + lane;
+    const bool occ = s < T.cap && T.keys[s] >= 0;
+    const uint64_t m = __ballot(occ);
+    if (occ) T.list[n_d + __popcll(m & ((1ULL << lane) - 1ULL))] = T.keys[s];
+    n_d += __popcll(m);
+  }
+  __syncthreads();
+  int pw = 1;
+  while (pw < n_d) pw <<= 1;
+  for (int s = n_d + lane; s < pw; s += kWave) T.list[s] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of list[0, pw)
+  for (int k = 2; k <= pw; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int x = lane; x < pw; x += kWave) {
+        int y = x ^ j;
+        if (y > x) {
+          int32_t u = T.list[x], v = T.list[y];
+          bool up = (x & k) == 0;
+          if ((u > v) == up) { T.list[x] = v; T.list[y] = u; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int r = lane; r < n_d; r += kWave) T.rank[hash_find(T.keys, T.shift, T.cap, T.list[r])] = r;
+  __syncthreads();
+  // entries per rank
+  for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
+    int32_t i = mem[t];
+    for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+      int32_t b = agg[col[e]];
+      if (b < 0) continue;
+      atomicAdd(&T.cursor[T.rank[hash_find(T.keys, T.shift, T.cap, b)]], 1);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the counts into start[], reset cursor
+  if (lane == 0) {
+    int run = 0;
+    for (int r = 0; r < n_d; ++r) { T.start[r] = run; run += T.cursor[r]; T.cursor[r] = 0; }
+  }
+  __syncthreads();
+  const int64_t row0 = crp[a];
+  const int64_t e0 = eoff[a];
+  for (int r = lane; r < n_d; r += kWave) {
+    ccol[row0 + r] = T.list[r];
+    crow[row0 + r] = (int32_t)a;
+    gl_ptr[row0 + r] = e0 + T.start[r];
+  }
+  // stable placement: entries in ascending fine order, 64 at a time
+  for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
+    int32_t i = mem[t];
+    for (int64_t eb = rp[i]; eb < rp[i + 1]; eb += kWave) {
+      int64_t e = eb + lane;
+      int myr = -1;
+      if (e < rp[i + 1]) {
+        int32_t b = agg[col[e]];
+        if (b >= 0) myr = T.rank[hash_find(T.keys, T.shift, T.cap, b)];
+      }
+      bool pending = myr >= 0;
+      uint64_t pend = __ballot(pending);
+      while (pend) {
+        int leader = __ffsll((long long)pend) - 1;
+        int R = __shfl(myr, leader, kWave);
+        uint64_t mask = __ballot(pending && myr == R);
+        if (pending && myr == R) {
+          int before = __popcll(mask & ((1ULL << lane) - 1ULL));
+          int64_t pos = e0 + T.start[R] + T.cursor[R] + before;
+          gl_idx[pos] = (int32_t)e;
+          gl_row[pos] = i;
+          pending = false;
+        }
+        __syncthreads();
+        if (lane == leader) T.cursor[R] += __popcll(mask);
+        __syncthreads();
+        pend &= ~mask;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// rowcnt[a] = distinct columns, elen[a] = connecting entries; a row that does
+// not fit the LDS table gets rowcnt[a] = -1 and raises *overflow (the host
+// then redoes it with k_gal_count_big)
 __global__ __launch_bounds__(kWave) void k_gal_count(int64_t na, const int64_t *__restrict__ ap,
                                                      const int32_t *__restrict__ mem,
                                                      const int64_t *__restrict__ rp,
@@ -584,34 +761,16 @@ __global__ __launch_bounds__(kWave) void k_gal_count(int64_t na, const int64_t *
                                                      int64_t *__restrict__ rowcnt,
                                                      int64_t *__restrict__ elen, int *overflow) {
   __shared__ int32_t keys[kHashCap];
-  __shared__ int nnew;
-  const int lane = threadIdx.x;
+  const GalTab T{keys, nullptr, nullptr, nullptr, nullptr, kHashCap, kHashShift};
   for (int64_t a = blockIdx.x; a < na; a += gridDim.x) {
-    for (int s = lane; s < kHashCap; s += kWave) keys[s] = -1;
-    if (lane == 0) nnew = 0;
-    __syncthreads();
-    int64_t tot = 0;
-    int full = 0;
-    for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
-      int32_t i = mem[t];
-      for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
-        int32_t b = agg[col[e]];
-        if (b < 0) continue;
-        ++tot;
-        int r = hash_insert(keys, b);
-        if (r == 1) atomicAdd(&nnew, 1);
-        else if (r < 0) full = 1;
-      }
-    }
-    tot = group_sum<kWave>(tot);
-    full = group_sum<kWave>(full);
-    __syncthreads();
-    if (lane == 0) {
-      rowcnt[a] = nnew;
+    int64_t nd, tot;
+    int full;
+    gal_count_row(a, ap, mem, rp, col, agg, T, &nd, &tot, &full);
+    if (threadIdx.x == 0) {
+      rowcnt[a] = full ? -1 : nd;
       elen[a] = tot;
       if (full) atomicExch(overflow, 1);
     }
-    __syncthreads();
   }
 }
 void launch_gal_count(int64_t na, const int64_t *ap, const int32_t *mem, const CsrView<double> &A,
@@ -622,128 +781,90 @@ void launch_gal_count(int64_t na, const int64_t *ap, const int32_t *mem, const C
   k_gal_count<<<grid, kWave, 0, s>>>(na, ap, mem, A.rowptr, A.col, agg, rowcnt, elen, overflow);
 }
 
+// table of big row q: 5 cap int32 at 5 toff[q] of the scratch, cap = tcap[q]
+__device__ __forceinline__ GalTab big_tab(int32_t *scratch, const int64_t *toff,
+                                          const int32_t *tcap, int q) {
+  const int cap = tcap[q];
+  int32_t *base = scratch + 5 * toff[q];
+  return GalTab{base, base + cap, base + 2 * cap, base + 3 * cap, base + 4 * cap, cap,
+                32 - (31 - __clz(cap))};
+}
+
+__global__ __launch_bounds__(kWave) void k_gal_count_big(
+    int nbig, const int32_t *__restrict__ rows, const int64_t *__restrict__ toff,
+    const int32_t *__restrict__ tcap, int32_t *scratch, const int64_t *__restrict__ ap,
+    const int32_t *__restrict__ mem, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const int32_t *__restrict__ agg,
+    int64_t *__restrict__ rowcnt, int *overflow) {
+  for (int q = blockIdx.x; q < nbig; q += gridDim.x) {
+    const GalTab T = big_tab(scratch, toff, tcap, q);
+    int64_t nd, tot;
+    int full;
+    gal_count_row(rows[q], ap, mem, rp, col, agg, T, &nd, &tot, &full);
+    if (threadIdx.x == 0) {
+      rowcnt[rows[q]] = nd;
+      if (full) atomicExch(overflow, 1);   // cannot happen: cap >= 2 entries
+    }
+  }
+}
+void launch_gal_count_big(int nbig, const int32_t *rows, const int64_t *toff, const int32_t *tcap,
+                          int32_t *scratch, const int64_t *ap, const int32_t *mem,
+                          const CsrView<double> &A, const int32_t *agg, int64_t *rowcnt,
+                          int *overflow, hipStream_t s) {
+  if (!nbig) return;
+  unsigned grid = (unsigned)(nbig < 65536 ? nbig : 65536);
+  k_gal_count_big<<<grid, kWave, 0, s>>>(nbig, rows, toff, tcap, scratch, ap, mem, A.rowptr,
+                                         A.col, agg, rowcnt, overflow);
+}
+
+// rows with more than kHashCap distinct columns are left to k_gal_fill_big
 __global__ __launch_bounds__(kWave) void k_gal_fill(
     int64_t na, const int64_t *__restrict__ ap, const int32_t *__restrict__ mem,
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const int32_t *__restrict__ agg, const int64_t *__restrict__ crp,
     const int64_t *__restrict__ eoff, int32_t *__restrict__ ccol, int32_t *__restrict__ crow,
-    int64_t *__restrict__ gl_ptr, int32_t *__restrict__ gl_idx, int32_t *__restrict__ gl_row,
-    int *overflow) {
-  __shared__ int32_t keys[kHashCap];   // coarse column per slot
-  __shared__ int32_t rank[kHashCap];   // sorted position of the slot's column
-  __shared__ int32_t list[kHashCap];   // distinct columns, then sorted
-  __shared__ int32_t start[kHashCap];  // list offset of each rank (within the row)
-  __shared__ int32_t cursor[kHashCap];
-  __shared__ int nd;
-  const int lane = threadIdx.x;
+    int64_t *__restrict__ gl_ptr, int32_t *__restrict__ gl_idx, int32_t *__restrict__ gl_row) {
+  __shared__ int32_t keys[kHashCap], rank[kHashCap], list[kHashCap], start[kHashCap],
+      cursor[kHashCap];
+  const GalTab T{keys, rank, list, start, cursor, kHashCap, kHashShift};
   for (int64_t a = blockIdx.x; a < na; a += gridDim.x) {
-    for (int s = lane; s < kHashCap; s += kWave) { keys[s] = -1; cursor[s] = 0; start[s] = 0; }
-    if (lane == 0) nd = 0;
-    __syncthreads();
-    int full = 0;
-    // distinct columns
-    for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
-      int32_t i = mem[t];
-      for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
-        int32_t b = agg[col[e]];
-        if (b < 0) continue;
-        if (hash_insert(keys, b) < 0) full = 1;
-      }
-    }
-    full = group_sum<kWave>(full);
-    if (full) {
-      if (lane == 0) atomicExch(overflow, 1);
-      __syncthreads();
-      continue;
-    }
-    __syncthreads();
-    for (int s = lane; s < kHashCap; s += kWave)
-      if (keys[s] >= 0) list[atomicAdd(&nd, 1)] = keys[s];
-    __syncthreads();
-    const int n_d = nd;
-    int pw = 1;
-    while (pw < n_d) pw <<= 1;
-    for (int s = n_d + lane; s < pw; s += kWave) list[s] = 0x7fffffff;
-    __syncthreads();
-    // bitonic sort of list[0, pw)
-    for (int k = 2; k <= pw; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int x = lane; x < pw; x += kWave) {
-          int y = x ^ j;
-          if (y > x) {
-            int32_t u = list[x], v = list[y];
-            bool up = (x & k) == 0;
-            if ((u > v) == up) { list[x] = v; list[y] = u; }
-          }
-        }
-        __syncthreads();
-      }
-    for (int r = lane; r < n_d; r += kWave) rank[hash_find(keys, list[r])] = r;
-    __syncthreads();
-    // entries per rank
-    for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
-      int32_t i = mem[t];
-      for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
-        int32_t b = agg[col[e]];
-        if (b < 0) continue;
-        atomicAdd(&cursor[rank[hash_find(keys, b)]], 1);
-      }
-    }
-    __syncthreads();
-    // exclusive scan of the counts into start[], reset cursor
-    if (lane == 0) {
-      int run = 0;
-      for (int r = 0; r < n_d; ++r) { start[r] = run; run += cursor[r]; cursor[r] = 0; }
-    }
-    __syncthreads();
-    const int64_t row0 = crp[a];
-    const int64_t e0 = eoff[a];
-    for (int r = lane; r < n_d; r += kWave) {
-      ccol[row0 + r] = list[r];
-      crow[row0 + r] = (int32_t)a;
-      gl_ptr[row0 + r] = e0 + start[r];
-    }
-    // stable placement: entries in ascending fine order, 64 at a time
-    for (int64_t t = ap[a]; t < ap[a + 1]; ++t) {
-      int32_t i = mem[t];
-      for (int64_t eb = rp[i]; eb < rp[i + 1]; eb += kWave) {
-        int64_t e = eb + lane;
-        int myr = -1;
-        if (e < rp[i + 1]) {
-          int32_t b = agg[col[e]];
-          if (b >= 0) myr = rank[hash_find(keys, b)];
-        }
-        bool pending = myr >= 0;
-        uint64_t pend = __ballot(pending);
-        while (pend) {
-          int leader = __ffsll((long long)pend) - 1;
-          int R = __shfl(myr, leader, kWave);
-          uint64_t mask = __ballot(pending && myr == R);
-          if (pending && myr == R) {
-            int before = __popcll(mask & ((1ULL << lane) - 1ULL));
-            int64_t pos = e0 + start[R] + cursor[R] + before;
-            gl_idx[pos] = (int32_t)e;
-            gl_row[pos] = i;
-            pending = false;
-          }
-          __syncthreads();
-          if (lane == leader) cursor[R] += __popcll(mask);
-          __syncthreads();
-          pend &= ~mask;
-        }
-      }
-    }
-    __syncthreads();
+    if (crp[a + 1] - crp[a] > kHashCap) continue;
+    gal_fill_row(a, ap, mem, rp, col, agg, crp, eoff, ccol, crow, gl_ptr, gl_idx, gl_row, T);
   }
 }
 void launch_gal_fill(int64_t na, const int64_t *ap, const int32_t *mem, const CsrView<double> &A,
                      const int32_t *agg, const int64_t *crp, const int64_t *eoff, int32_t *ccol,
                      int32_t *crow, int64_t *gl_ptr, int32_t *gl_idx, int32_t *gl_row,
-                     int *overflow, hipStream_t s) {
+                     hipStream_t s) {
   if (!na) return;
   unsigned grid = (unsigned)(na < 65536 ? na : 65536);
   k_gal_fill<<<grid, kWave, 0, s>>>(na, ap, mem, A.rowptr, A.col, agg, crp, eoff, ccol, crow,
-                                    gl_ptr, gl_idx, gl_row, overflow);
+                                    gl_ptr, gl_idx, gl_row);
+}
+
+__global__ __launch_bounds__(kWave) void k_gal_fill_big(
+    int nbig, const int32_t *__restrict__ rows, const int64_t *__restrict__ toff,
+    const int32_t *__restrict__ tcap, int32_t *scratch, const int64_t *__restrict__ ap,
+    const int32_t *__restrict__ mem, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const int32_t *__restrict__ agg,
+    const int64_t *__restrict__ crp, const int64_t *__restrict__ eoff, int32_t *__restrict__ ccol,
+    int32_t *__restrict__ crow, int64_t *__restrict__ gl_ptr, int32_t *__restrict__ gl_idx,
+    int32_t *__restrict__ gl_row) {
+  for (int q = blockIdx.x; q < nbig; q += gridDim.x) {
+    const GalTab T = big_tab(scratch, toff, tcap, q);
+    gal_fill_row(rows[q], ap, mem, rp, col, agg, crp, eoff, ccol, crow, gl_ptr, gl_idx, gl_row,
+                 T);
+  }
+}
+void launch_gal_fill_big(int nbig, const int32_t *rows, const int64_t *toff, const int32_t *tcap,
+                         int32_t *scratch, const int64_t *ap, const int32_t *mem,
+                         const CsrView<double> &A, const int32_t *agg, const int64_t *crp,
+                         const int64_t *eoff, int32_t *ccol, int32_t *crow, int64_t *gl_ptr,
+                         int32_t *gl_idx, int32_t *gl_row, hipStream_t s) {
+  if (!nbig) return;
+  unsigned grid = (unsigned)(nbig < 65536 ? nbig : 65536);
+  k_gal_fill_big<<<grid, kWave, 0, s>>>(nbig, rows, toff, tcap, scratch, ap, mem, A.rowptr, A.col,
+                                        agg, crp, eoff, ccol, crow, gl_ptr, gl_idx, gl_row);
 }
 
 __global__ void k_gal_mirror(int64_t nnzc, const int32_t *__restrict__ crow,

@@ -58,7 +58,8 @@ void launch_s_pow_scale(const SegTab &t, double *w, const double *diag, double *
                         double *partials, hipStream_t s);
 void launch_s_pow_normalize(const SegTab &t, const double *w, const double *nrm2, double *v,
                             hipStream_t s);
-// out[2 seg] = v^T Av, out[2 seg + 1] = sum (v_i diag_i) v_i
+// out[3 seg] = v^T Av, out[3 seg + 1] = sum (v_i diag_i) v_i,
+// out[3 seg + 2] = sum Av_i (Av_i / diag_i)
 void launch_s_rayleigh(const SegTab &t, const double *v, const double *Av, const double *diag,
                        double *out, double *partials, hipStream_t s);
 void launch_s_pow_init(const SegTab &t, uint64_t salt, int level, double *v, hipStream_t s);

@@ -6,6 +6,10 @@
 
 namespace mgpbd {
 
+// *bad = 1 unless rp[0..n] / col[0..nnz) form a valid CSR (bounds monotone
+// within [0, nnz], rp[0] = 0, columns in [0, n) strictly ascending per row)
+void launch_validate_csr(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col, int *bad,
+                         hipStream_t s);
 void launch_diagpos(int64_t n, const int64_t *rp, const int32_t *col, int64_t *dpos, int *bad,
                     hipStream_t s);
 // diag[i] = A_ii, dinv = 1 / A_ii (FP64, optional FP32 copy); bad = 1 if some A_ii <= 0
@@ -50,13 +54,29 @@ void launch_normalize(int64_t na, const int64_t *ap, const int32_t *mem, const d
 
 // Galerkin symbolic: per coarse row a, distinct coarse columns and the fine
 // entries that feed each coarse entry in ascending fine order
+// rowcnt[a] = distinct coarse columns of aggregate row a (-1 when they do not
+// fit the LDS table: *overflow is raised and launch_gal_count_big redoes it),
+// elen[a] = fine entries connecting it to other aggregates
 void launch_gal_count(int64_t na, const int64_t *ap, const int32_t *mem, const CsrView<double> &A,
                       const int32_t *agg, int64_t *rowcnt, int64_t *elen, int *overflow,
                       hipStream_t s);
+// rows[q] (q < nbig) with a table of tcap[q] slots (a power of two) at
+// 5 toff[q] int32 of scratch
+void launch_gal_count_big(int nbig, const int32_t *rows, const int64_t *toff, const int32_t *tcap,
+                          int32_t *scratch, const int64_t *ap, const int32_t *mem,
+                          const CsrView<double> &A, const int32_t *agg, int64_t *rowcnt,
+                          int *overflow, hipStream_t s);
+// sorted columns and Galerkin lists of the rows with at most 1024 distinct
+// columns; the others are left to launch_gal_fill_big
 void launch_gal_fill(int64_t na, const int64_t *ap, const int32_t *mem, const CsrView<double> &A,
                      const int32_t *agg, const int64_t *crp, const int64_t *eoff, int32_t *ccol,
                      int32_t *crow, int64_t *gl_ptr, int32_t *gl_idx, int32_t *gl_row,
-                     int *overflow, hipStream_t s);
+                     hipStream_t s);
+void launch_gal_fill_big(int nbig, const int32_t *rows, const int64_t *toff, const int32_t *tcap,
+                         int32_t *scratch, const int64_t *ap, const int32_t *mem,
+                         const CsrView<double> &A, const int32_t *agg, const int64_t *crp,
+                         const int64_t *eoff, int32_t *ccol, int32_t *crow, int64_t *gl_ptr,
+                         int32_t *gl_idx, int32_t *gl_row, hipStream_t s);
 void launch_gal_mirror(int64_t nnzc, const int32_t *crow, const int32_t *ccol, const int64_t *crp,
                        int32_t *mirror, int *bad, hipStream_t s);
 void launch_gal_numeric(int64_t nnzc, const int32_t *crow, const int32_t *ccol,

@@ -241,7 +241,16 @@ void Solver::tune_lanes(int l) {
 }
 
 // omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min) for each body,
-// lambda_max from the power method and a Rayleigh quotient (Sec. 4.5)
+// lambda_max from the power method (Sec. 4.5): v <- D^-1 A v / |D^-1 A v|
+// from a positive pseudo-random start. At step power_iters and then every
+// kPowerCheck steps the Rayleigh quotient theta = v^T A v / v^T D v and the
+// eigen-residual |D^-1 A v - theta v|_D are formed from the step's own
+// product A v; a body stops once the residual is at most power_tol theta
+// |v|_D (or at step power_max) and keeps that theta. With w = A v,
+// |D^-1 w - theta v|_D^2 = sum w_i^2 / d_i - theta v^T w. Bodies are
+// independent (block-diagonal A, per-body normalisation), so iterating a body
+// past its stop does not change the others.
+static constexpr int kPowerCheck = 10;
 void Solver::power_omega(int l) {
   Level &L = *lev[l];
   const int ns = (int)L.seg.size() - 1;
@@ -249,23 +258,45 @@ void Solver::power_omega(int l) {
   L.lmax.assign(ns, 0.0);
   if (L.n == 0) return;
   SegTab t = L.tab.view();
-  dscal.reserve(std::max<size_t>(16, 3 * (size_t)ns + 8));
+  dscal.reserve(std::max<size_t>(16, 4 * (size_t)ns + 8));
   double *nrm2 = dscal.p, *ray = dscal.p + ns;
   double *v = L.r.p, *w = L.t.p;
   launch_s_pow_init(t, stream_salt(opt.seed, kStreamPowerStart), l, v, st);
   CsrView<double> A = L.view();
-  for (int it = 0; it < opt.power_iters; ++it) {
+  std::vector<double> theta(ns, 0.0), h(3 * (size_t)ns);
+  std::vector<char> stopped(ns, 0);
+  // a body without rows has no estimate to make
+  int left = 0;
+  for (int k = 0; k < ns; ++k) {
+    if (L.seg[k + 1] == L.seg[k]) stopped[k] = 1;
+    else ++left;
+  }
+  for (int it = 0; left > 0; ++it) {
     launch_spmv<double>(A, v, w, st);
+    const bool last = it >= opt.power_max;
+    if (last || (it >= opt.power_iters && (it - opt.power_iters) % kPowerCheck == 0)) {
+      launch_s_rayleigh(t, v, w, L.diag.p, ray, partials(), st);
+      MG_HIP(hipMemcpyAsync(h.data(), ray, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, st));
+      MG_HIP(hipStreamSynchronize(st));
+      for (int k = 0; k < ns; ++k) {
+        if (stopped[k]) continue;
+        const double s1 = h[3 * k], s2 = h[3 * k + 1], s3 = h[3 * k + 2];
+        const double th = s1 / s2;
+        const double res2 = s3 - th * s1;
+        const double res = res2 > 0.0 ? std::sqrt(res2) : 0.0;
+        theta[k] = th;
+        if (last || res <= opt.power_tol * th * std::sqrt(s2)) {
+          stopped[k] = 1;
+          --left;
+        }
+      }
+      if (left == 0) break;
+    }
     launch_s_pow_scale(t, w, L.diag.p, nrm2, partials(), st);
     launch_s_pow_normalize(t, w, nrm2, v, st);
   }
-  launch_spmv<double>(A, v, w, st);
-  launch_s_rayleigh(t, v, w, L.diag.p, ray, partials(), st);
-  std::vector<double> h(2 * (size_t)ns);
-  MG_HIP(hipMemcpyAsync(h.data(), ray, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, st));
-  MG_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < ns; ++k) {
-    L.lmax[k] = opt.lmax_scale * (h[2 * k] / h[2 * k + 1]);
+    L.lmax[k] = opt.lmax_scale * theta[k];
     L.omega[k] = 2.0 / (L.lmax[k] + opt.lambda_min);
   }
 }
@@ -470,9 +501,13 @@ void Solver::build_members(int l) {
   launch_sort_segments(na, L.agg_ptr.p, L.agg_mem.p, st);
 }
 
-void Solver::galerkin_symbolic(int l) {
+// Aggregate-level symbolic Galerkin counts of level l into ltmp (distinct
+// coarse columns per aggregate row) and ltmp2 (connecting fine entries). Rows
+// whose columns do not fit the LDS table of k_gal_count are counted again
+// with a table in global memory of at least twice their entries; big keeps
+// those rows and tables for the fill.
+void Solver::gal_count_rows(int l, BigRows &big) {
   Level &L = *lev[l];
-  Level &C = *lev[l + 1];
   const int64_t na = L.n_agg;
   CsrView<double> A = L.view();
   ltmp.reserve(na + 1);
@@ -480,8 +515,53 @@ void Solver::galerkin_symbolic(int l) {
   reset_flags();
   launch_gal_count(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, ltmp.p, ltmp2.p,
                    flags.p + kFOverflow, st);
-  MG_REQUIRE(read_flag(kFOverflow) == 0, MGPBD_E_SETUP,
-             "a coarse row has more distinct columns than the symbolic table holds");
+  big.n = 0;
+  if (read_flag(kFOverflow) == 0) return;
+  std::vector<int64_t> cnt(na), el(na);
+  ltmp.download(cnt.data(), na, st);
+  ltmp2.download(el.data(), na, st);
+  MG_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> rows, caps;
+  std::vector<int64_t> offs;
+  int64_t tot = 0;
+  for (int64_t a = 0; a < na; ++a) {
+    if (cnt[a] >= 0) continue;
+    int64_t cap = 2048;
+    while (cap < 2 * el[a]) cap <<= 1;
+    MG_REQUIRE(cap <= ((int64_t)1 << 30), MGPBD_E_SETUP, "aggregate row too long");
+    rows.push_back((int32_t)a);
+    caps.push_back((int32_t)cap);
+    offs.push_back(tot);
+    tot += cap;
+  }
+  big.n = (int)rows.size();
+  big.rows.upload(rows.data(), rows.size(), st);
+  big.tcap.upload(caps.data(), caps.size(), st);
+  big.toff.upload(offs.data(), offs.size(), st);
+  big.scratch.alloc(5 * (size_t)tot);
+  reset_flags();
+  launch_gal_count_big(big.n, big.rows.p, big.toff.p, big.tcap.p, big.scratch.p, L.agg_ptr.p,
+                       L.agg_mem.p, A, L.agg.p, ltmp.p, flags.p + kFOverflow, st);
+  MG_REQUIRE(read_flag(kFOverflow) == 0, MGPBD_E_SETUP, "symbolic Galerkin table overflow");
+}
+
+void Solver::gal_fill_rows(int l, const BigRows &big, const int64_t *crp, const int64_t *eoff,
+                           int32_t *ccol, int32_t *crow) {
+  Level &L = *lev[l];
+  CsrView<double> A = L.view();
+  launch_gal_fill(L.n_agg, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, crp, eoff, ccol, crow,
+                  L.gl_ptr.p, L.gl_idx.p, L.gl_row.p, st);
+  launch_gal_fill_big(big.n, big.rows.p, big.toff.p, big.tcap.p, big.scratch.p, L.agg_ptr.p,
+                      L.agg_mem.p, A, L.agg.p, crp, eoff, ccol, crow, L.gl_ptr.p, L.gl_idx.p,
+                      L.gl_row.p, st);
+}
+
+void Solver::galerkin_symbolic(int l) {
+  Level &L = *lev[l];
+  Level &C = *lev[l + 1];
+  const int64_t na = L.n_agg;
+  BigRows big;
+  gal_count_rows(l, big);
   C.n = na;
   C.rowptr.alloc(na + 1);
   scan_exclusive_i64(ltmp.p, C.rowptr.p, na, scan_tmp, st);
@@ -498,15 +578,13 @@ void Solver::galerkin_symbolic(int l) {
   L.gl_idx.alloc(std::max<int64_t>(nlist, 1));
   L.gl_row.alloc(std::max<int64_t>(nlist, 1));
   reset_flags();
-  launch_gal_fill(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, C.rowptr.p, eoff.p, C.col.p, C.crow.p,
-                  L.gl_ptr.p, L.gl_idx.p, L.gl_row.p, flags.p + kFOverflow, st);
+  gal_fill_rows(l, big, C.rowptr.p, eoff.p, C.col.p, C.crow.p);
   MG_HIP(hipMemcpyAsync(L.gl_ptr.p + C.nnz, eoff.p + na, sizeof(int64_t),
                         hipMemcpyDeviceToDevice, st));
   launch_gal_mirror(C.nnz, C.crow.p, C.col.p, C.rowptr.p, C.mirror.p, flags.p + kFMirror, st);
   int *h = static_cast<int *>(pinned);
   MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
-  MG_REQUIRE(h[kFOverflow] == 0, MGPBD_E_SETUP, "symbolic Galerkin table overflow");
   MG_REQUIRE(h[kFMirror] == 0, MGPBD_E_SETUP, "coarse pattern is not symmetric");
   C.val.alloc(C.nnz);
   if (mixed()) C.val32.alloc(C.nnz);
@@ -548,14 +626,8 @@ void Solver::galerkin_symbolic_k(int l) {
   Level &L = *lev[l];
   Level &C = *lev[l + 1];
   const int64_t na = L.n_agg;
-  CsrView<double> A = L.view();
-  ltmp.reserve(na + 1);
-  ltmp2.reserve(na + 1);
-  reset_flags();
-  launch_gal_count(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, ltmp.p, ltmp2.p,
-                   flags.p + kFOverflow, st);
-  MG_REQUIRE(read_flag(kFOverflow) == 0, MGPBD_E_SETUP,
-             "a coarse row has more distinct columns than the symbolic table holds");
+  BigRows big;
+  gal_count_rows(l, big);
   L.arp.alloc(na + 1);
   scan_exclusive_i64(ltmp.p, L.arp.p, na, scan_tmp, st);
   DevBuf<int64_t> eoff;
@@ -572,15 +644,13 @@ void Solver::galerkin_symbolic_k(int l) {
   L.gl_idx.alloc(std::max<int64_t>(nlist, 1));
   L.gl_row.alloc(std::max<int64_t>(nlist, 1));
   reset_flags();
-  launch_gal_fill(na, L.agg_ptr.p, L.agg_mem.p, A, L.agg.p, L.arp.p, eoff.p, L.acol.p, L.acrow.p,
-                  L.gl_ptr.p, L.gl_idx.p, L.gl_row.p, flags.p + kFOverflow, st);
+  gal_fill_rows(l, big, L.arp.p, eoff.p, L.acol.p, L.acrow.p);
   MG_HIP(hipMemcpyAsync(L.gl_ptr.p + L.annz, eoff.p + na, sizeof(int64_t),
                         hipMemcpyDeviceToDevice, st));
   launch_gal_mirror(L.annz, L.acrow.p, L.acol.p, L.arp.p, L.amirror.p, flags.p + kFMirror, st);
   int *h = static_cast<int *>(pinned);
   MG_HIP(hipMemcpyAsync(h, flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
-  MG_REQUIRE(h[kFOverflow] == 0, MGPBD_E_SETUP, "symbolic Galerkin table overflow");
   MG_REQUIRE(h[kFMirror] == 0, MGPBD_E_SETUP, "coarse pattern is not symmetric");
   // expansion into unknowns
   L.cstart.alloc(an);

@@ -184,6 +184,15 @@ class Solver {
   void candidate0();
   void colour_level(int l);
   void build_members(int l);
+  // aggregate rows whose symbolic Galerkin tables live in global memory
+  struct BigRows {
+    int n = 0;
+    DevBuf<int32_t> rows, tcap, scratch;
+    DevBuf<int64_t> toff;
+  };
+  void gal_count_rows(int l, BigRows &big);
+  void gal_fill_rows(int l, const BigRows &big, const int64_t *crp, const int64_t *eoff,
+                     int32_t *ccol, int32_t *crow);
   void galerkin_symbolic(int l);
   void galerkin_numeric(int l);
   int64_t qr_level(int l);

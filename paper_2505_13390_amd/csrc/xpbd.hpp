@@ -11,7 +11,7 @@ void launch_predict(int64_t nv, const double *w, const double *g, double dt, dou
 // rows with kind[r] != 0 (ARAP) are skipped; kind may be null (no ARAP rows)
 void launch_constraints(int64_t m, const int32_t *rv, const int8_t *kind, const double *rest_c,
                         const double *const *xyz, double *C, double *grad, hipStream_t s);
-// ARAP rows (Sec. 6): C = |F - R|_F^2 with F = Ds Dm^-1 and R the nearest
+// ARAP rows (Sec. 5.3, Eq. 8): C = |F - R|_F^2 with F = Ds Dm^-1 and R the nearest
 // rotation (det +1) of F; grad slot k = column k - 1 of 2 (F - R) Dm^-T
 // (k = 1..3), slot 0 the negated sum. Only rows with kind[r] != 0.
 void launch_arap_constraints(int64_t m, const int32_t *rv, const int8_t *kind,

@@ -10,7 +10,8 @@ from paper_2505_13390_amd import workloads as W
 
 COMMON = ("theta", "gs_sweeps", "pre_sweeps", "post_sweeps", "lambda_min", "coarse_max",
           "dense_max", "max_levels", "power_iters", "omega_relax", "tol", "max_pcg", "seed",
-          "reuse_interval", "b_mode", "eps_b", "lmax_scale", "smoother", "n_cand")
+          "reuse_interval", "b_mode", "eps_b", "lmax_scale", "smoother", "n_cand", "power_max",
+          "power_tol")
 
 
 def log(*a):

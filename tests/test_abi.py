@@ -49,6 +49,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.matrix_free == 1
     assert o.smoother == 0
     assert o.n_cand == 1
+    assert o.power_max == 500 and o.power_tol == 1e-2
 
 
 def test_null_arguments_rejected_without_device_work():

@@ -1,4 +1,4 @@
-"""GPU parity of the ARAP constraint rows (Sec. 6, As-Rigid-As-Possible
+"""GPU parity of the ARAP constraint rows (Sec. 5.3, Eq. 8, As-Rigid-As-Possible
 constraints) against the FP64 oracle, on the 8x8x32 ARAP beam (12,288 tet
 rows, mu 1e9, dt 10 ms) and smaller ragged beams.
 

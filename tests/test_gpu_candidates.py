@@ -192,3 +192,70 @@ def test_solve_entry_with_six_candidates():
     assert np.linalg.norm(A @ x - b) <= 1.01e-7 * np.linalg.norm(b)
     assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
     B.mgpbd_destroy(ctx)
+
+
+def hub_matrix(size, n_leaves, weak=1e-3):
+    """Block diagonal of (n_leaves + 1) cliques of `size` nodes (diagonal
+    `size`, off-diagonal -1: strongly coupled, SPD), plus weak couplings -weak
+    (below the strength threshold, so the aggregates are the cliques) from
+    each node of clique 0 to one node of n_leaves / size distinct leaf
+    cliques: the coarse row of clique 0 meets n_leaves + 1 distinct coarse
+    columns."""
+    import scipy.sparse as sp
+    nc = n_leaves + 1
+    per = n_leaves // size
+    r, c = np.divmod(np.arange(size * size), size)
+    blocks = np.arange(nc)[:, None] * size
+    rows = (blocks + r[None, :]).ravel()
+    cols = (blocks + c[None, :]).ravel()
+    vals = np.where(np.tile(r == c, nc), float(size), -1.0)
+    i = np.repeat(np.arange(size), per)
+    k = np.tile(np.arange(per), size)
+    leaf = size * (1 + i * per + k) + (k % size)
+    rows = np.concatenate([rows, i, leaf])
+    cols = np.concatenate([cols, leaf, i])
+    vals = np.concatenate([vals, np.full(2 * i.size, -weak)])
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(size * nc, size * nc))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("K", [1, 6])
+def test_symbolic_galerkin_row_beyond_the_lds_table(K):
+    """An aggregate whose coarse row meets 2,401 distinct coarse columns, more
+    than the 1,024 the LDS table of the symbolic Galerkin kernels holds: that
+    row is done with a table in global memory, and the hierarchy equals the
+    oracle's bit for bit (Eq. 6), for one candidate and for six (cliques of
+    eight, two levels, the second smoothed only)."""
+    size = 4 if K == 1 else 8
+    A = hub_matrix(size, 2400)
+    rp, col, val = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    kw = dict(n_cand=K) if K == 1 else dict(n_cand=K, max_levels=2)
+    oo, go = opts(**kw)
+    h = O.Hier.build(rp, col, val, oo)
+    orp, _, _ = h.matrix(1)
+    assert np.diff(orp).max() >= 2401
+    b = np.random.default_rng(0).standard_normal(A.shape[0])
+    xo, st = h.pcg(b, 1e-8, 1000)
+    ctx = B.mgpbd_solver_create(go)
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")
+    xg = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
+    r = B.mgpbd_solve(ctx, dev(rp, torch.int64), dev(col, torch.int32), dev(val, torch.float64),
+                      dev(b, torch.float64), 1e-8, xg)
+    log("hub K=%d: iters oracle %d gpu %d" % (K, st["iters"], r["iters"]))
+    assert r["status"] == B.OK
+    if K == 1:
+        L = B.mgpbd_num_levels(ctx)
+        assert L == h.levels
+        assert same(B.mgpbd_get_aggregates(ctx, 0), h.transfer(0)[0])
+        for l in range(L):
+            gr, gc, gv = B.mgpbd_get_matrix(ctx, l)
+            hr, hc, hv = h.matrix(l)
+            assert same(gr, hr) and same(gc, hc) and same(gv, hv), l
+    else:
+        compare_hierarchy_k(h, ctx, K, "hub K=6")
+    x = xg.cpu().numpy()
+    assert np.linalg.norm(A @ x - b) <= 2e-8 * np.linalg.norm(b)
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+    B.mgpbd_destroy(ctx)
