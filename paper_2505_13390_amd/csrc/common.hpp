@@ -35,6 +35,9 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;        // threads per block for streaming kernels
 constexpr int kMaxGrid = 2048;     // blocks of a streaming kernel (8 per CU on 256 CUs)
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
+// Most partial sums one block of a reduction writes (partials[k * grid + block],
+// k < kMaxBlockSums); the shared partials buffer holds this many per block.
+constexpr int kMaxBlockSums = 3;
 
 // Owning device buffer.
 template <class T>

@@ -57,6 +57,7 @@ __device__ __forceinline__ void block_range(int64_t items, int64_t &lo, int64_t 
 // would write back the XCD's L2 from every block).
 template <int NV>
 __device__ void block_partials(const double (&v)[NV], double *partials) {
+  static_assert(NV <= kMaxBlockSums, "the partials buffer holds kMaxBlockSums sums per block");
   __shared__ double sh[NV][kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;

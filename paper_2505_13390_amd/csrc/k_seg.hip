@@ -47,6 +47,7 @@ void SegTable::build(const std::vector<int64_t> &offsets, hipStream_t s) {
 // block partials in block-table order: partials[k * nblk + table index]
 template <int NV>
 __device__ void seg_partials(const double (&v)[NV], double *partials) {
+  static_assert(NV <= kMaxBlockSums, "the partials buffer holds kMaxBlockSums sums per block");
   __shared__ double sh[NV][kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;

@@ -23,7 +23,7 @@ Solver::Solver(const mgpbd_options &o) : opt(o) {
   nlev = 1;
   ctl.alloc(1);
   all_done.alloc(1);
-  red_partials.alloc(2 * (size_t)kMaxGrid + 64);
+  red_partials.alloc(kMaxBlockSums * (size_t)kMaxGrid + 64);
   dscal.alloc(16);
   flags.alloc(kNumFlags);
   amax.alloc(1);
@@ -46,7 +46,7 @@ void Solver::ensure_pinned(size_t bytes) {
 }
 
 void Solver::ensure_partials(int nblk) {
-  red_partials.reserve(2 * (size_t)std::max(nblk, kMaxGrid) + 64);
+  red_partials.reserve(kMaxBlockSums * (size_t)std::max(nblk, kMaxGrid) + 64);
 }
 
 void Solver::set_stream(hipStream_t s) {
