@@ -17,8 +17,8 @@
  *    torch.Tensor.data_ptr() of a cuda tensor on the current device). They
  *    are borrowed for the duration of the call only; work is ordered on the
  *    context's stream (mgpbd_set_stream; default: a stream the context creates) and every
- *    call returns after that work has completed, except mgpbd_apply, which only
- *    enqueues its kernels.
+ *    call returns after that work has completed, except mgpbd_apply and
+ *    mgpbd_apply_noalloc, which only enqueue their kernels.
  *  - Arrays documented as "host" are ordinary CPU memory, read or written
  *    during the call only.
  *  - The library never frees caller memory; mgpbd_destroy frees everything
@@ -262,6 +262,20 @@ mgpbd_status mgpbd_get_matrix(const mgpbd_ctx *ctx, int32_t l, int64_t *rowptr, 
    enqueued on the context's stream (no synchronisation). Errors: E_STATE
    before the first step. */
 mgpbd_status mgpbd_apply(mgpbd_ctx *ctx, const double *x, double *y);
+/* mgpbd_apply for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same y = A x with the same kernels, but it calls no hipMalloc, hipFree or
+   allocating library routine. The matrix-free vertex gather's vector
+   (4 FP64 per vertex) lives in a library-static device array of 16 MiB per
+   GPU, held until the process ends, so the context may have at most 524,288
+   vertices (E_INVALID_ARG beyond that, nothing enqueued); the CSR form
+   (matrix_free = 0) uses no scratch. Every call on a GPU shares that GPU's
+   array, so calls that overlap in time on one GPU (on different streams or
+   from different threads) race and give undefined results. x, y: device FP64
+   [m], not aliased; enqueued on the context's stream (no synchronisation);
+   the context's device must be current (E_INVALID_ARG otherwise). Errors:
+   E_STATE before the first step. */
+mgpbd_status mgpbd_apply_noalloc(mgpbd_ctx *ctx, const double *x, double *y);
 /* The K > 1 transfer of level l (n_cand > 1 only, E_STATE otherwise): host kq
    [n_agg] (coarse unknowns of each aggregate), coff [n_agg + 1] (first coarse
    unknown of each), Q [members][n_cand] (P's row of each aggregate member, in

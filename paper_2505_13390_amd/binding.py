@@ -91,6 +91,7 @@ _SIGS = {
     "mgpbd_get_transfer": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mgpbd_get_matrix": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mgpbd_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mgpbd_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mgpbd_get_qr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     "mgpbd_get_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -344,6 +345,19 @@ def mgpbd_apply(ctx, x, y):
     else:
         px, py = _dev(x, torch.float64), _dev(y, torch.float64)
     _check(ctx, lib().mgpbd_apply(ctx, px, py))
+
+
+def mgpbd_apply_noalloc(ctx, x, y):
+    """mgpbd_apply through the entry point that allocates nothing (its gather
+    vector lives in the library's static per-GPU scratch array)."""
+    import torch
+    m, _ = mgpbd_num_rows(ctx)
+    if m > 0:
+        px = _vec(x, torch.float64, m, "x")
+        py = _vec(y, torch.float64, m, "y")
+    else:
+        px, py = _dev(x, torch.float64), _dev(y, torch.float64)
+    _check(ctx, lib().mgpbd_apply_noalloc(ctx, px, py))
 
 
 def mgpbd_get_qr(ctx, l, n, n_agg, n_mem, K):

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "solver.hpp"
 #include "xpbd.hpp"
@@ -26,6 +27,7 @@ struct Timer {
 struct mgpbd_ctx {
   std::string err;
   mgpbd_options opt;
+  int device = -1;                 // the HIP device current at creation
   hipStream_t own = nullptr;
   hipStream_t st = nullptr;
   std::unique_ptr<Solver> solver;
@@ -67,7 +69,36 @@ struct mgpbd_batch {
   DevBuf<double> pos[3], vel[3];
 };
 
+// Scratch of mgpbd_apply_noalloc: the matrix-free vertex gather's u[nv][4]
+// (FP64) for callers that cannot allocate. Each GPU holds one copy until the
+// process ends, shared by every call on that GPU. In host code `scratch` is
+// only a stand-in for the device array: its device address on each GPU comes
+// from hipGetSymbolAddress (scratch_addr) and only that address is handed to
+// kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Look up this device's copy of `scratch` once (the device must be current).
+void scratch_setup(int dev) {
+  MG_REQUIRE(dev >= 0 && dev < kMaxDevices, MGPBD_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[dev]) return;
+  void *p = nullptr;
+  MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  MG_REQUIRE(p != nullptr, MGPBD_E_DEVICE, "no device address for the scratch array");
+  g_scratch_addr[dev] = p;
+}
+
+void *scratch_addr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDevices ? g_scratch_addr[dev] : nullptr;
+}
 
 mgpbd_status fail(mgpbd_ctx *c, const Error &e) {
   if (c) c->err = e.what();
@@ -123,6 +154,8 @@ void check_options(const mgpbd_options &o) {
 void init_ctx(mgpbd_ctx *c, const mgpbd_options *opt) {
   if (opt) c->opt = *opt; else mgpbd_default_options(&c->opt);
   check_options(c->opt);
+  MG_HIP(hipGetDevice(&c->device));
+  scratch_setup(c->device);
   MG_HIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   c->st = c->own;
   c->solver.reset(new Solver(c->opt));
@@ -716,6 +749,28 @@ mgpbd_status mgpbd_apply(mgpbd_ctx *c, const double *x, double *y) {
     return MGPBD_E_STATE;
   }
   return guard(c, [&] { c->solver->apply_fine(x, y); });
+}
+
+mgpbd_status mgpbd_apply_noalloc(mgpbd_ctx *c, const double *x, double *y) {
+  if (!c || !x || !y || x == y) return MGPBD_E_INVALID_ARG;
+  if (!c->has_body || !c->have_rhs) {
+    c->err = "no assembled system: run a step first";
+    return MGPBD_E_STATE;
+  }
+  return guard(c, [&] {
+    int dev = -1;
+    MG_HIP(hipGetDevice(&dev));
+    MG_REQUIRE(dev == c->device, MGPBD_E_INVALID_ARG,
+               "the context's device must be current");
+    const size_t need = sizeof(double) * 4 * (size_t)c->nv;
+    MG_REQUIRE(need <= kNoAllocScratchBytes, MGPBD_E_INVALID_ARG,
+               "mgpbd_apply_noalloc: " + std::to_string(c->nv) + " vertices need " +
+                   std::to_string(need) + " bytes of scratch, more than the " +
+                   std::to_string(kNoAllocScratchBytes) + " it holds");
+    void *u = scratch_addr(c->device);
+    MG_REQUIRE(u != nullptr, MGPBD_E_STATE, "scratch address not set up for this device");
+    c->solver->apply_fine_into(x, y, static_cast<double *>(u));
+  });
 }
 
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *c, double *b) {

@@ -1099,6 +1099,19 @@ void Solver::apply_fine(const double *x, double *y) {
   }
 }
 
+void Solver::apply_fine_into(const double *x, double *y, double *u) {
+  Level &F = *lev[0];
+  MG_REQUIRE(F.n > 0 && F.val.p, MGPBD_E_STATE, "no assembled matrix");
+  if (mf.ok()) {
+    MfView<double> v = mf;
+    v.u = u;
+    launch_mf_gather(v, x, nullptr, st);
+    launch_mf_rows_dot(v, x, y, nullptr, nullptr, st);
+  } else {
+    launch_spmv_dot_partials(F.view(), x, y, nullptr, nullptr, st);
+  }
+}
+
 std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, int max_iters,
                                    const int32_t *force) {
   MG_REQUIRE(built, MGPBD_E_STATE, "solve without a hierarchy");

@@ -144,6 +144,9 @@ class Solver {
   // [nb]) fixes iteration counts. One result per body.
   // y = A x on the fine level with the PCG loop's own kernels (no sync)
   void apply_fine(const double *x, double *y);
+  // the same product with the matrix-free gather vector in the caller's u
+  // ([nv][4]) and no partial sums: allocates nothing
+  void apply_fine_into(const double *x, double *y, double *u);
   std::vector<PcgResult> pcg(const double *b, double *x_out, double tol, int max_iters,
                              const int32_t *force);
   double *dl() { return x.p; }   // internal PCG iterate
