@@ -168,11 +168,15 @@ def bench_batch(args, B, W):
     n_iters = args.iters or ws[0].iters
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
-                                  matrix_free=1 if args.fine == "mf" else 0,
+                                  matrix_free={"mf": 1, "csr": 0, "auto": 2}[args.fine],
                                   lmax_scale=args.lmax_scale or 1.05,
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
+    if args.vcycle_tail is not None:
+        opt.vcycle_tail = args.vcycle_tail
+    if args.fuse_transfers is not None:
+        opt.fuse_transfers = args.fuse_transfers
     rows = [w.n_rows for w in ws]
     t0 = time.perf_counter()
     bodies = [B.Body(w, opt) for w in ws]
@@ -245,7 +249,8 @@ def bench_batch(args, B, W):
                             "%d batch(es) of %s bodies" % (len(groups),
                                                            "/".join(str(len(g)) for g in groups))),
                    "iters_per_frame": n_iters, "precision": args.precision,
-                   "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
+                   "fine_operator": {"mf": "matrix-free", "csr": "csr",
+                                     "auto": "timed choice"}[args.fine],
                    "smoother": args.smoother,
                    "pcg_budget_per_solve": int(opt.max_pcg),
                    "solves_at_tol": int((ratios <= 1e-6).sum()), "solves": int(ratios.size),
@@ -285,8 +290,9 @@ def main():
     ap.add_argument("--max-pcg", type=int, default=None,
                     help="PCG iteration budget per solve (default 500 for C2 and C4, whose "
                          "solves cannot reach 1e-6 in a benchmark's time; 5000 otherwise)")
-    ap.add_argument("--fine", default="mf", choices=["mf", "csr"],
-                    help="fine-level products: matrix-free (default) or assembled CSR")
+    ap.add_argument("--fine", default="mf", choices=["mf", "csr", "auto"],
+                    help="fine-level products: matrix-free (default), assembled CSR, or the "
+                         "faster of the two timed at the first setup")
     ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev", "gs"],
                     help="V-cycle smoother (Sec. 4.5): omega-Jacobi (default), Chebyshev or "
                          "multicolour Gauss-Seidel")
@@ -296,6 +302,12 @@ def main():
     ap.add_argument("--candidates", type=int, default=1,
                     help="near-kernel candidates per level (Sec. 4.3 generates six); 1 is the "
                          "one-candidate hierarchy of the headline line")
+    ap.add_argument("--vcycle-tail", type=int, default=None,
+                    help="rows per body at or below which the coarse V-cycle levels run as one "
+                         "fused launch (default 0 = one launch per pass)")
+    ap.add_argument("--fuse-transfers", type=int, default=None, choices=[0, 1],
+                    help="1: residual + restriction in one pass and the prolongation folded into "
+                         "the first post-sweep; 0 (default): separate transfer kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-frames", action="store_true",
                     help="time each kernel of every PCG product inside the timed frames with HIP "
@@ -335,10 +347,14 @@ def main():
                                   lmax_scale=args.lmax_scale, n_cand=args.candidates,
                                   b_mode=1 if args.candidate == "ones" else 0,
                                   profile_spmv=1 if args.profile_frames else 0,
-                                  matrix_free=1 if args.fine == "mf" else 0,
+                                  matrix_free={"mf": 1, "csr": 0, "auto": 2}[args.fine],
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
+    if args.vcycle_tail is not None:
+        opt.vcycle_tail = args.vcycle_tail
+    if args.fuse_transfers is not None:
+        opt.fuse_transfers = args.fuse_transfers
     t0 = time.perf_counter()
     body = B.Body(w, opt)
     print("created %s: %d rows, %d entries in %.1f s" % (w.name, body.m, body.nnz,
@@ -387,7 +403,8 @@ def main():
     B.mgpbd_set_stream(body.ctx, 0)
     del xp, yp
     traffic = None
-    if args.fine == "mf":
+    is_mf = B.mgpbd_get_fine_operator(body.ctx) == 1
+    if is_mf:
         ne, nvol = int(w.edges.shape[0]), int(w.vol_tet.shape[0])
         nar = int(w.arap_tet.shape[0])
         gb, rb = mf_bytes(body.m, int(w.n_verts), 2 * ne + 4 * nvol + 4 * nar, ne, nvol, nar)
@@ -429,6 +446,12 @@ def main():
                                                       1)}}
     nl = B.mgpbd_num_levels(body.ctx)
     lv = [B.mgpbd_get_level(body.ctx, l) for l in range(nl)]
+    if spmv_calls:
+        # each level's own V-cycle passes per V-cycle (levels inside the fused
+        # tail are timed on its first level)
+        ncyc = sum(r["vcycles"] for r in res)
+        roof["timed_region"]["vcycle_level_us"] = [
+            round(1e3 * sum(r["ms_level"][l] for r in res) / max(ncyc, 1), 2) for l in range(nl)]
     out = {
         "metric": METRIC, "value": value, "unit": "constraint-DOF*iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_frame,
@@ -437,7 +460,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "rows": body.m, "nnz": body.nnz,
                    "iters_per_frame": n_iters, "precision": args.precision,
-                   "fine_operator": "matrix-free" if args.fine == "mf" else "csr",
+                   "fine_operator": ("matrix-free" if is_mf else "csr") +
+                                    (" (timed choice)" if args.fine == "auto" else ""),
                    "smoother": args.smoother, "reuse_interval": args.reuse, "tol": 1e-6,
                    "lmax_scale": args.lmax_scale, "candidates": args.candidates,
                    "candidate": args.candidate,
@@ -450,6 +474,11 @@ def main():
                        "max": float(max(r["pcg_ratio"].max() for r in res))},
                    "ms_pcg_per_frame": 1e3 * pcg_s / args.steps,
                    "ms_setup_per_frame": sum(r["ms_setup"] for r in res) / args.steps,
+                   "ms_galerkin_per_frame": sum(r["ms_galerkin"] for r in res) / args.steps,
+                   "ms_assembly_per_frame": sum(r["ms_assembly"] for r in res) / args.steps,
+                   "ms_update_per_frame": sum(r["ms_update"] for r in res) / args.steps,
+                   "vcycle_tail": int(opt.vcycle_tail),
+                   "fuse_transfers": int(opt.fuse_transfers),
                    "levels": [x["n"] for x in lv],
                    "operator_complexity": round(sum(x["nnz"] for x in lv) / lv[0]["nnz"], 4)},
         "roofline": roof,

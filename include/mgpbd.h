@@ -80,7 +80,9 @@ typedef struct {
   int32_t profile_spmv; /* time every fine-level A p product with HIP events (the PCG
                            loop then launches kernels directly, without the graph): 0 */
   int32_t spmv_tile;    /* CSR pass variant: 0 = autotuned on levels with >= 20000 rows
-                           (timed at setup), -1 = lanes-per-row kernels only,
+                           (timed at setup: lanes-per-row kernels, LDS stream kernels,
+                           SELL-C-sigma), -1 = lanes-per-row kernels only, -2 =
+                           SELL-C-sigma (C = 64, sigma = 1024) on every level,
                            1024 / 2048 / 4096 = LDS stream kernels with that tile: 0 */
   int32_t spmv_lanes;   /* lanes per row of the lanes-per-row kernels when not autotuned
                            (4, 8, 16, 32, 64; 0 = from the mean row length): 0 */
@@ -88,8 +90,10 @@ typedef struct {
                            smoother sweeps, residual) apply J W J^T + alpha~ from the
                            constraint gradients instead of the assembled values (the
                            assembled A still feeds the setup, the Galerkin products and
-                           the Jacobi diagonal); 0: assembled CSR. Simulation contexts
-                           only; mgpbd_solve always uses the caller's CSR: 1 */
+                           the Jacobi diagonal); 0: assembled CSR; 2: whichever of the
+                           two is faster for this context's fine level, timed at its
+                           first setup (for a batch, for the whole system). Simulation
+                           contexts only; mgpbd_solve always uses the caller's CSR: 1 */
   int32_t smoother;     /* V-cycle smoother (Sec. 4.5): 0 = omega-Jacobi, 1 = Chebyshev
                            (pre_sweeps / post_sweeps steps of Chebyshev acceleration of
                            Jacobi on [lambda_min, lmax_scale * lambda_max] of D^-1 A,
@@ -109,6 +113,20 @@ typedef struct {
                            |D^-1 A v - theta v|_D <= power_tol * theta * |v|_D
                            (|x|_D = sqrt(x^T D x)) or at step power_max; lambda_max =
                            theta. power_max = power_iters gives a fixed count: 1e-2 */
+  int32_t vcycle_tail;  /* coarse levels on which every body has at most this many rows run
+                           as one launch per V-cycle, one workgroup per body, from the
+                           first such level down to the dense solve and back (same
+                           arithmetic as the per-level kernels; Jacobi and Chebyshev
+                           smoothers, one candidate); 0 = one launch per pass (the
+                           default: one workgroup's passes are latency-bound and slower
+                           than the launches they replace on the workloads measured): 0 */
+  int32_t fuse_transfers; /* 1: with one candidate, the residual and the restriction are one
+                           pass on assembled levels, and the prolongation is folded into
+                           the first post-smoothing step (its input z + P e is formed on
+                           the fly); 0: separate residual, restriction and prolongation
+                           kernels (the default: the fused passes' extra dependent loads
+                           cost more than the launches they save on the workloads
+                           measured): 0 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.
@@ -159,7 +177,7 @@ typedef struct {
   double *pcg_ratio;    /* final recurrence |r| / |b| of each solve */
   int32_t *setup_ran;   /* 1 where the AMG setup ran at that iteration */
   int32_t iters_done;   /* global iterations executed */
-  double ms_setup;      /* time spent in setup (hipEvents) */
+  double ms_setup;      /* time spent in the setup and in the Galerkin refreshes (hipEvents) */
   double ms_pcg;        /* time spent in the PCG loops (hipEvents) */
   double ms_total;      /* whole frame (hipEvents) */
   int64_t spmv_calls;   /* fine-level A p launches timed (profile_spmv) */
@@ -167,6 +185,15 @@ typedef struct {
                            the one-block dot finisher) */
   double spmv_first_ms; /* summed duration of the first kernel alone (the matrix-free
                            vertex gather; 0 for the CSR product) */
+  double ms_assembly;   /* constraints, gradients and the assembly of A and b (Eq. 3) */
+  double ms_galerkin;   /* iterations that reuse the hierarchy (Sec. 4.2): Galerkin
+                           products of the coarse levels (Eq. 6), diagonals and the
+                           coarsest factor; part of ms_setup */
+  double ms_update;     /* dx = M^-1 gradC^T dlambda (Eq. 5), lambda and x updates */
+  int64_t vcycles;      /* V-cycles timed level by level (profile_spmv only) */
+  double ms_level[16];  /* with profile_spmv: each level's own V-cycle passes (smoothing,
+                           residual, transfers, dense solve; not its coarser levels)
+                           summed over the timed V-cycles; 0 otherwise */
 } mgpbd_step_stats;
 
 typedef struct {
@@ -283,6 +310,10 @@ mgpbd_status mgpbd_apply_noalloc(mgpbd_ctx *ctx, const double *x, double *y);
    level's candidates); any may be NULL. */
 mgpbd_status mgpbd_get_qr(const mgpbd_ctx *ctx, int32_t l, int32_t *kq, int64_t *coff, double *Q,
                           double *B);
+/* *matrix_free = 1 when the fine-level passes use the constraint-gradient
+   operator, 0 when they read the assembled values (after the first step; with
+   options.matrix_free = 2 this is the timed choice) */
+mgpbd_status mgpbd_get_fine_operator(const mgpbd_ctx *ctx, int32_t *matrix_free);
 /* right-hand side b of the last global iteration, host FP64 [m] */
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *ctx, double *b);
 /* Lagrange multipliers lambda of the current frame, host FP64 [m] */

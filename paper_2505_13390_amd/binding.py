@@ -31,7 +31,8 @@ class Options(C.Structure):
                 ("use_graph", C.c_int32), ("profile_spmv", C.c_int32),
                 ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32),
                 ("matrix_free", C.c_int32), ("smoother", C.c_int32), ("n_cand", C.c_int32),
-                ("power_max", C.c_int32), ("power_tol", C.c_double)]
+                ("power_max", C.c_int32), ("power_tol", C.c_double),
+                ("vcycle_tail", C.c_int32), ("fuse_transfers", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -53,7 +54,17 @@ class StepStats(C.Structure):
     _fields_ = [("bnorm", C.c_void_p), ("pcg_iters", C.c_void_p), ("pcg_ratio", C.c_void_p),
                 ("setup_ran", C.c_void_p), ("iters_done", C.c_int32), ("ms_setup", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("spmv_calls", C.c_int64),
-                ("spmv_ms", C.c_double), ("spmv_first_ms", C.c_double)]
+                ("spmv_ms", C.c_double), ("spmv_first_ms", C.c_double),
+                ("ms_assembly", C.c_double), ("ms_galerkin", C.c_double),
+                ("ms_update", C.c_double), ("vcycles", C.c_int64),
+                ("ms_level", C.c_double * 16)]
+
+
+def _phase_fields(st, levels):
+    """The per-phase timers of a filled StepStats (levels: how many of
+    ms_level to report)."""
+    return dict(ms_assembly=st.ms_assembly, ms_galerkin=st.ms_galerkin, ms_update=st.ms_update,
+                vcycles=st.vcycles, ms_level=[st.ms_level[l] for l in range(levels)])
 
 
 class SolveStats(C.Structure):
@@ -94,6 +105,7 @@ _SIGS = {
     "mgpbd_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mgpbd_get_qr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
+    "mgpbd_get_fine_operator": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "mgpbd_get_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_lambda": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgpbd_get_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -240,7 +252,7 @@ def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
     ratio = np.zeros(n)
     setup = np.zeros(n, np.int32)
     st = StepStats(_np_ptr(bn).value, _np_ptr(its).value, _np_ptr(ratio).value,
-                   _np_ptr(setup).value, 0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+                   _np_ptr(setup).value)
     _prepare(ctx)
     s = lib().mgpbd_step(ctx, _dev(x, f64), _dev(y, f64), _dev(z, f64), _dev(vx, f64),
                          _dev(vy, f64), _dev(vz, f64), int(n_iters),
@@ -249,7 +261,8 @@ def mgpbd_step(ctx, x, y, z, vx, vy, vz, n_iters: int, stats: bool = True):
     k = st.iters_done
     return dict(bnorm=bn[:k], pcg_iters=its[:k], pcg_ratio=ratio[:k], setup_ran=setup[:k],
                 iters_done=k, ms_setup=st.ms_setup, ms_pcg=st.ms_pcg, ms_total=st.ms_total,
-                spmv_calls=st.spmv_calls, spmv_ms=st.spmv_ms, spmv_first_ms=st.spmv_first_ms)
+                spmv_calls=st.spmv_calls, spmv_ms=st.spmv_ms, spmv_first_ms=st.spmv_first_ms,
+                **_phase_fields(st, 16))
 
 
 def mgpbd_solve(ctx, rowptr, col, val, b, tol, x_out):
@@ -370,6 +383,13 @@ def mgpbd_get_qr(ctx, l, n, n_agg, n_mem, K):
     return kq, coff, Q, B
 
 
+def mgpbd_get_fine_operator(ctx):
+    """1 when the fine-level passes are matrix-free, 0 when assembled"""
+    v = C.c_int32(0)
+    _check(ctx, lib().mgpbd_get_fine_operator(ctx, C.byref(v)))
+    return int(v.value)
+
+
 def mgpbd_get_rhs(ctx, m):
     out = np.zeros(m)
     _check(ctx, lib().mgpbd_get_rhs(ctx, _np_ptr(out)))
@@ -437,8 +457,7 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
     sts = (StepStats * nb)()
     for k, a in enumerate(arrs):
         sts[k] = StepStats(_np_ptr(a["bnorm"]).value, _np_ptr(a["pcg_iters"]).value,
-                           _np_ptr(a["pcg_ratio"]).value, _np_ptr(a["setup_ran"]).value,
-                           0, 0.0, 0.0, 0.0, 0, 0.0, 0.0)
+                           _np_ptr(a["pcg_ratio"]).value, _np_ptr(a["setup_ran"]).value)
     sys_ctx = mgpbd_batch_context(batch)
     _prepare(sys_ctx)
     st = lib().mgpbd_batch_step(batch, xs, vs, int(n_iters), sts if stats else None)
@@ -450,7 +469,8 @@ def mgpbd_batch_step(batch, xyz_list, vxyz_list, n_iters, stats: bool = True):
                         pcg_ratio=a["pcg_ratio"][:d], setup_ran=a["setup_ran"][:d],
                         iters_done=d, ms_setup=sts[k].ms_setup, ms_pcg=sts[k].ms_pcg,
                         ms_total=sts[k].ms_total, spmv_calls=sts[k].spmv_calls,
-                        spmv_ms=sts[k].spmv_ms, spmv_first_ms=sts[k].spmv_first_ms))
+                        spmv_ms=sts[k].spmv_ms, spmv_first_ms=sts[k].spmv_first_ms,
+                        **_phase_fields(sts[k], 16)))
     return out
 
 

@@ -24,10 +24,37 @@ struct Timer {
   }
 };
 
+// Events recorded around the phases of a frame and read once after the
+// frame's last synchronisation (no extra host round trip per phase); the
+// pool grows to the largest frame and is reused.
+struct PhaseEvents {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  ~PhaseEvents() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  void reset() { used = 0; }
+  size_t mark(hipStream_t s) {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      MG_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    MG_HIP(hipEventRecord(pool[used], s));
+    return used++;
+  }
+  double ms(size_t a, size_t b) const {
+    float v = 0.f;
+    MG_HIP(hipEventElapsedTime(&v, pool[a], pool[b]));
+    return v;
+  }
+};
+
 struct mgpbd_ctx {
   std::string err;
   mgpbd_options opt;
   int device = -1;                 // the HIP device current at creation
+  PhaseEvents phase;               // assembly and update timers of the frame
   hipStream_t own = nullptr;
   hipStream_t st = nullptr;
   std::unique_ptr<Solver> solver;
@@ -105,6 +132,9 @@ mgpbd_status fail(mgpbd_ctx *c, const Error &e) {
   return (mgpbd_status)e.status;
 }
 
+// Runs f and turns its exceptions into a status. A failed HIP call also
+// leaves the runtime's per-thread last error set; it is cleared here so that
+// it cannot surface later in the caller's own, unrelated HIP calls.
 template <class F>
 mgpbd_status guard(mgpbd_ctx *c, F f) {
   try {
@@ -112,11 +142,14 @@ mgpbd_status guard(mgpbd_ctx *c, F f) {
     if (c) c->err.clear();
     return MGPBD_OK;
   } catch (const Error &e) {
+    (void)hipGetLastError();
     return fail(c, e);
   } catch (const std::bad_alloc &) {
+    (void)hipGetLastError();
     if (c) c->err = "host allocation failed";
     return MGPBD_E_OUT_OF_MEMORY;
   } catch (const std::exception &e) {
+    (void)hipGetLastError();
     if (c) c->err = e.what();
     return MGPBD_E_DEVICE;
   }
@@ -134,18 +167,21 @@ void check_options(const mgpbd_options &o) {
   MG_REQUIRE(o.power_iters >= 0 && o.power_max >= 0 && o.max_pcg >= 1 && o.check_every >= 1,
              MGPBD_E_INVALID_ARG, "iteration counts");
   MG_REQUIRE(o.power_tol >= 0.0 && std::isfinite(o.power_tol), MGPBD_E_INVALID_ARG, "power_tol");
+  MG_REQUIRE(o.vcycle_tail >= 0, MGPBD_E_INVALID_ARG, "vcycle_tail");
+  MG_REQUIRE(o.fuse_transfers == 0 || o.fuse_transfers == 1, MGPBD_E_INVALID_ARG,
+             "fuse_transfers must be 0 or 1");
   MG_REQUIRE(o.tol >= 0.0 && o.lmax_scale > 0.0, MGPBD_E_INVALID_ARG, "tol / lmax_scale");
   MG_REQUIRE(o.precision == MGPBD_PREC_FP64 || o.precision == MGPBD_PREC_MIXED,
              MGPBD_E_INVALID_ARG, "precision");
   MG_REQUIRE(o.reuse_interval >= 0, MGPBD_E_INVALID_ARG, "reuse_interval");
-  MG_REQUIRE(o.spmv_tile == 0 || o.spmv_tile == -1 || o.spmv_tile == 1024 ||
-                 o.spmv_tile == 2048 || o.spmv_tile == 4096,
-             MGPBD_E_INVALID_ARG, "spmv_tile must be 0, -1, 1024, 2048 or 4096");
+  MG_REQUIRE(o.spmv_tile == 0 || o.spmv_tile == -1 || o.spmv_tile == -2 ||
+                 o.spmv_tile == 1024 || o.spmv_tile == 2048 || o.spmv_tile == 4096,
+             MGPBD_E_INVALID_ARG, "spmv_tile must be 0, -1, -2, 1024, 2048 or 4096");
   MG_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 4 || o.spmv_lanes == 8 || o.spmv_lanes == 16 ||
                  o.spmv_lanes == 32 || o.spmv_lanes == 64,
              MGPBD_E_INVALID_ARG, "spmv_lanes must be 0, 4, 8, 16, 32 or 64");
-  MG_REQUIRE(o.matrix_free == 0 || o.matrix_free == 1, MGPBD_E_INVALID_ARG,
-             "matrix_free must be 0 or 1");
+  MG_REQUIRE(o.matrix_free >= 0 && o.matrix_free <= 2, MGPBD_E_INVALID_ARG,
+             "matrix_free must be 0, 1 or 2");
   MG_REQUIRE(o.smoother >= 0 && o.smoother <= 2, MGPBD_E_INVALID_ARG,
              "smoother must be 0 (omega-Jacobi), 1 (Chebyshev) or 2 (Gauss-Seidel)");
   MG_REQUIRE(o.n_cand >= 1 && o.n_cand <= 8, MGPBD_E_INVALID_ARG, "n_cand must be in 1..8");
@@ -282,10 +318,10 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
   double *oxyz[3] = {c->old[0].p, c->old[1].p, c->old[2].p};
   Timer total, part;
   total.start(st);
-  double ms_setup = 0.0, ms_pcg = 0.0;
-  S.spmv_calls = 0;
-  S.spmv_ms = 0.0;
-  S.spmv_first_ms = 0.0;
+  double ms_setup = 0.0, ms_pcg = 0.0, ms_galerkin = 0.0;
+  S.reset_profile();
+  c->phase.reset();
+  std::vector<std::pair<size_t, size_t>> asm_ev, upd_ev;
   launch_predict(nv, c->w.p, c->g, c->dt, xyz, vxyz, oxyz, st);
   if (m == 0) {
     // no constraint rows: every global iteration is empty, the frame is the
@@ -302,6 +338,11 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
         stats[k].spmv_calls = 0;
         stats[k].spmv_ms = 0.0;
         stats[k].spmv_first_ms = 0.0;
+        stats[k].ms_assembly = 0.0;
+        stats[k].ms_galerkin = 0.0;
+        stats[k].ms_update = 0.0;
+        stats[k].vcycles = 0;
+        for (double &v : stats[k].ms_level) v = 0.0;
       }
     return;
   }
@@ -312,6 +353,7 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
   std::vector<int32_t> fv(nb, 0);
   int n_stopped = 0;
   for (int ite = 0; ite < n_iters && n_stopped < nb; ++ite) {
+    const size_t a0 = c->phase.mark(st);
     const int8_t *kind = c->has_arap ? c->kind.p : nullptr;
     launch_constraints(m, c->rv.p, kind, c->rest_c.p, xyz, c->C.p, c->grad.p, st);
     if (kind) launch_arap_constraints(m, c->rv.p, kind, c->dm_inv.p, xyz, c->C.p, c->grad.p, st);
@@ -332,6 +374,7 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
         MG_HIP(hipMemsetAsync(c->b.p + c->roff[k], 0,
                               sizeof(double) * (c->roff[k + 1] - c->roff[k]), st));
     c->have_rhs = true;
+    asm_ev.emplace_back(a0, c->phase.mark(st));
     std::vector<double> bn = S.norm2(c->b.p);
     for (auto &v : bn) v = std::sqrt(v);
     const int R = c->opt.reuse_interval;
@@ -348,7 +391,9 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
     } else {
       S.refresh();
     }
-    ms_setup += part.stop(st);
+    const double ms_s = part.stop(st);
+    ms_setup += ms_s;
+    if (!due) ms_galerkin += ms_s;
     for (int k = 0; k < nb; ++k) {
       const std::vector<int32_t> *f = k < (int)force.size() ? force[k] : nullptr;
       fv[k] = (!stopped[k] && f && ite < (int)f->size()) ? (*f)[ite] : 0;
@@ -364,9 +409,11 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
                  "PCG breakdown (p^T A p <= 0 or r^T z <= 0)" +
                      (nb > 1 ? " in body " + std::to_string(k) : std::string()));
     }
+    const size_t u0 = c->phase.mark(st);
     launch_dx_update(nv, c->vptr.p, c->vrow.p, c->vslot.p, c->grad.p, S.dl(), c->w.p,
                      c->opt.omega_relax, xyz, st);
     launch_lambda_add(m, c->lambda.p, S.dl(), st);
+    upd_ev.emplace_back(u0, c->phase.mark(st));
     for (int k = 0; k < nb; ++k) {
       if (stopped[k]) continue;
       iters_done[k] = ite + 1;
@@ -375,7 +422,10 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
   }
   launch_velocity(nv, c->dt, xyz, oxyz, vxyz, st);
   c->frame++;
-  double ms_total = total.stop(st);
+  double ms_total = total.stop(st);   // synchronises: every phase event has completed
+  double ms_asm = 0.0, ms_upd = 0.0;
+  for (auto &e : asm_ev) ms_asm += c->phase.ms(e.first, e.second);
+  for (auto &e : upd_ev) ms_upd += c->phase.ms(e.first, e.second);
   if (stats)
     for (int k = 0; k < nb; ++k) {
       stats[k].iters_done = iters_done[k];
@@ -385,6 +435,12 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
       stats[k].spmv_calls = S.spmv_calls;
       stats[k].spmv_ms = S.spmv_ms;
       stats[k].spmv_first_ms = S.spmv_first_ms;
+      stats[k].ms_assembly = ms_asm;
+      stats[k].ms_galerkin = ms_galerkin;
+      stats[k].ms_update = ms_upd;
+      stats[k].vcycles = S.vcycles;
+      for (int l = 0; l < 16; ++l)
+        stats[k].ms_level[l] = l < Solver::kProfLevels ? S.level_ms[l] : 0.0;
     }
 }
 
@@ -421,6 +477,8 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->n_cand = 1;
   o->power_max = 500;
   o->power_tol = 1e-2;
+  o->vcycle_tail = 0;
+  o->fuse_transfers = 0;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {
@@ -771,6 +829,13 @@ mgpbd_status mgpbd_apply_noalloc(mgpbd_ctx *c, const double *x, double *y) {
     MG_REQUIRE(u != nullptr, MGPBD_E_STATE, "scratch address not set up for this device");
     c->solver->apply_fine_into(x, y, static_cast<double *>(u));
   });
+}
+
+mgpbd_status mgpbd_get_fine_operator(const mgpbd_ctx *c, int32_t *matrix_free) {
+  if (!c || !matrix_free) return MGPBD_E_INVALID_ARG;
+  if (!c->has_body || !c->solver->built) return MGPBD_E_STATE;
+  *matrix_free = c->solver->mf.ok() ? 1 : 0;
+  return MGPBD_OK;
 }
 
 mgpbd_status mgpbd_get_rhs(const mgpbd_ctx *c, double *b) {

@@ -4,6 +4,8 @@
 // dense coarsest solve, and the FP64 PCG loop with deterministic grid
 // reductions and a device-resident control block (no host round trip per
 // iteration; every kernel returns at once when the solve is finished).
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "rowops.hpp"
 
@@ -115,6 +117,90 @@ __global__ __launch_bounds__(kBlock) void k_stream(const int *done, int64_t ntil
   }
 }
 
+// SELL-C-sigma kernel: one wavefront per chunk of 64 rows, lane t owns slot
+// t of the chunk and adds its row's entries in column order (padding adds
+// exact zeros), then applies the epilogue to the row it holds.
+template <class T, class In, class Op>
+__global__ __launch_bounds__(kBlock) void k_sell(const int *done, SellView<T> S, In x, Op op,
+                                                 double *partials) {
+  if (done && *done) return;
+  constexpr int WPB = kBlock / kWave;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  int64_t lo, hi;
+  block_range(S.nchunks, lo, hi);
+  double acc = 0.0;
+  for (int64_t c = lo + wv; c < hi; c += WPB) {
+    const int64_t b = S.ptr[c], len = (S.ptr[c + 1] - b) / kSellC;
+    const int32_t row = S.perm[c * kSellC + lane];
+    T s = 0;
+    for (int64_t k = 0; k < len; ++k) {
+      const int64_t e = b + k * kSellC + lane;
+      s += S.val[e] * x(S.col[e]);
+    }
+    if (row >= 0) op(row, s, acc);
+  }
+  if (partials) {
+    double v[1] = {acc};
+    block_partials<1>(v, partials);
+  }
+}
+
+void build_sell(const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
+                std::vector<int32_t> &perm, std::vector<int64_t> &ptr,
+                std::vector<int32_t> &scol, std::vector<int64_t> &slot) {
+  const int64_t n = (int64_t)rp.size() - 1;
+  const int64_t nchunks = (n + kSellC - 1) / kSellC;
+  perm.assign(nchunks * kSellC, -1);
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  for (int64_t w0 = 0; w0 < n; w0 += kSellSigma) {
+    const int64_t w1 = std::min<int64_t>(n, w0 + kSellSigma);
+    std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) {
+      return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+    });
+  }
+  for (int64_t i = 0; i < n; ++i) perm[i] = order[i];
+  ptr.assign(nchunks + 1, 0);
+  for (int64_t c = 0; c < nchunks; ++c) {
+    int64_t len = 0;
+    for (int t = 0; t < kSellC; ++t) {
+      const int32_t r = perm[c * kSellC + t];
+      if (r >= 0) len = std::max<int64_t>(len, rp[r + 1] - rp[r]);
+    }
+    ptr[c + 1] = ptr[c] + len * kSellC;
+  }
+  scol.assign(ptr[nchunks], 0);
+  slot.assign(rp[n], 0);
+  for (int64_t c = 0; c < nchunks; ++c)
+    for (int t = 0; t < kSellC; ++t) {
+      const int32_t r = perm[c * kSellC + t];
+      if (r < 0) continue;
+      for (int64_t k = 0; k < rp[r + 1] - rp[r]; ++k) {
+        const int64_t pos = ptr[c] + k * kSellC + t;
+        scol[pos] = col[rp[r] + k];
+        slot[rp[r] + k] = pos;
+      }
+    }
+}
+
+template <class S, class T>
+__global__ void k_sell_values(int64_t nnz, const int64_t *__restrict__ slot,
+                              const S *__restrict__ val, T *__restrict__ sval) {
+  int64_t lo, hi;
+  block_range(nnz, lo, hi);
+  for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) sval[slot[e]] = (T)val[e];
+}
+template <class S, class T>
+void launch_sell_values(int64_t nnz, const int64_t *slot, const S *val, T *sval, hipStream_t s) {
+  if (nnz) k_sell_values<S, T><<<grid_for(nnz, kBlock), kBlock, 0, s>>>(nnz, slot, val, sval);
+}
+template void launch_sell_values<double, double>(int64_t, const int64_t *, const double *,
+                                                 double *, hipStream_t);
+template void launch_sell_values<double, float>(int64_t, const int64_t *, const double *,
+                                                float *, hipStream_t);
+template void launch_sell_values<float, float>(int64_t, const int64_t *, const float *, float *,
+                                               hipStream_t);
+
 #define MG_DISPATCH_TILE(tile, LAUNCH) \
   switch (tile) {                      \
     case 1024: LAUNCH(1024); break;    \
@@ -126,6 +212,11 @@ template <class T, class In, class Op>
 static int launch_pass(const CsrView<T> &A, In x, Op op, const int *done, double *partials,
                        hipStream_t s) {
   if (A.n == 0) return 0;
+  if (A.sell.val) {
+    const int grid = grid_for(A.sell.nchunks * kWave, kBlock);
+    k_sell<T, In, Op><<<grid, kBlock, 0, s>>>(done, A.sell, x, op, partials);
+    return grid;
+  }
   if (A.tile > 0) {
     int grid = grid_for(A.ntiles, 1);
     if (A.nt) {
@@ -238,6 +329,67 @@ void launch_cheb(const CsrView<T> &A, const T *r, const T *dinv, const T *coef,
 }
 
 template <class T>
+void launch_jacobi_prolong(const CsrView<T> &A, const T *wdinv, const T *r, const T *zi,
+                           const T *p, const int32_t *agg, const T *e, T *zo, const int *done,
+                           hipStream_t s) {
+  const InProlong<T> in{zi, p, e, agg};
+  launch_pass<T>(A, in, OpJacobi<T, InProlong<T>>{wdinv, r, in, zo}, done, nullptr, s);
+}
+template <class T>
+void launch_cheb_prolong(const CsrView<T> &A, const T *r, const T *dinv, const T *coef,
+                         const int32_t *rowseg, int steps, int k, const T *zi, const T *p,
+                         const int32_t *agg, const T *e, T *d, T *zo, const int *done,
+                         hipStream_t s) {
+  const InProlong<T> in{zi, p, e, agg};
+  launch_pass<T>(A, in, OpCheb<T, InProlong<T>>{r, dinv, d, zo, coef, rowseg, steps, k, in},
+                 done, nullptr, s);
+}
+
+// Residual and restriction in one pass: G lanes per aggregate walk its member
+// rows in ascending order; each row's product sums with the fixed lane tree of
+// k_rows, and the aggregate's sum adds p_i (r_i - (A z)_i) member by member.
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_residual_restrict(
+    const int *done, int64_t na, const int64_t *__restrict__ ap, const int32_t *__restrict__ mem,
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ col, const T *__restrict__ val,
+    const T *__restrict__ r, const T *__restrict__ z, const T *__restrict__ p,
+    T *__restrict__ rc) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(na, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    const int64_t a = base + grp;
+    const bool ok = a < hi;
+    const int64_t m0 = ok ? ap[a] : 0, m1 = ok ? ap[a + 1] : 0;
+    T acc = 0;
+    for (int64_t t = m0; t < m1; ++t) {
+      const int32_t i = mem[t];
+      const int64_t e0 = rp[i], e1 = rp[i + 1];
+      T s = 0;
+#pragma unroll 4
+      for (int64_t e = e0 + sub; e < e1; e += G) s += val[e] * z[col[e]];
+      s = group_sum<G, T>(s);
+      acc += p[i] * (r[i] - s);
+    }
+    if (ok && sub == 0) rc[a] = acc;
+  }
+}
+template <class T>
+void launch_residual_restrict(const CsrView<T> &A, const T *r, const T *z, int64_t na,
+                              const int64_t *ap, const int32_t *mem, const T *p, T *rc,
+                              const int *done, hipStream_t s) {
+  if (na == 0) return;
+  const int G = A.lanes;
+  const int grid = grid_for(na * G, kBlock);
+#define L_(GG) k_residual_restrict<GG, T><<<grid, kBlock, 0, s>>>(done, na, ap, mem, A.rowptr, \
+                                                                 A.col, A.val, r, z, p, rc)
+  MG_DISPATCH_G(G, L_);
+#undef L_
+}
+
+template <class T>
 void launch_residual(const CsrView<T> &A, const T *r, const T *z, T *res, const int *done,
                      hipStream_t s) {
   launch_pass<T>(A, InVec<T>{z}, OpResidual<T>{r, res}, done, nullptr, s);
@@ -266,6 +418,42 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t na, const int64_t *
     }
     s = group_sum<G>(s);
     if (ok && sub == 0) rc[a] = s;
+  }
+}
+
+// the restriction's member sums when the terms p_i res_i are already stored
+// (same lanes, order and tree as k_restrict, so the same bits)
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_restrict_sum(int64_t na,
+                                                         const int64_t *__restrict__ ap,
+                                                         const int32_t *__restrict__ mem,
+                                                         const T *__restrict__ w,
+                                                         T *__restrict__ rc, const int *done) {
+  if (done && *done) return;
+  constexpr int R = kBlock / G;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  int64_t lo, hi;
+  block_range(na, lo, hi);
+  for (int64_t base = lo; base < hi; base += R) {
+    int64_t a = base + grp;
+    bool ok = a < hi;
+    int64_t b0 = ok ? ap[a] : 0, b1 = ok ? ap[a + 1] : 0;
+    T s = 0;
+    for (int64_t k = b0 + sub; k < b1; k += G) s += w[mem[k]];
+    s = group_sum<G>(s);
+    if (ok && sub == 0) rc[a] = s;
+  }
+}
+template <class T>
+void launch_restrict_sum(int64_t na, const int64_t *ap, const int32_t *mem, const T *w, T *rc,
+                         int lanes, const int *done, hipStream_t s) {
+  if (na == 0) return;
+  const int grid = grid_for(na * lanes, kBlock);
+  switch (lanes) {
+    case 64: k_restrict_sum<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
+    case 32: k_restrict_sum<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
+    case 16: k_restrict_sum<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
+    default: k_restrict_sum<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
   }
 }
 
@@ -507,6 +695,18 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
                                int, int, const T *, T *, T *, const int *, hipStream_t);            \
   template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
                                    T *, int, const int *, hipStream_t);                             \
+  template void launch_restrict_sum<T>(int64_t, const int64_t *, const int32_t *, const T *, T *,  \
+                                       int, const int *, hipStream_t);                             \
+  template void launch_jacobi_prolong<T>(const CsrView<T> &, const T *, const T *, const T *,     \
+                                         const T *, const int32_t *, const T *, T *, const int *, \
+                                         hipStream_t);                                            \
+  template void launch_cheb_prolong<T>(const CsrView<T> &, const T *, const T *, const T *,       \
+                                       const int32_t *, int, int, const T *, const T *,           \
+                                       const int32_t *, const T *, T *, T *, const int *,         \
+                                       hipStream_t);                                              \
+  template void launch_residual_restrict<T>(const CsrView<T> &, const T *, const T *, int64_t,    \
+                                            const int64_t *, const int32_t *, const T *, T *,     \
+                                            const int *, hipStream_t);                            \
   template void launch_prolong<T>(int64_t, const int32_t *, const T *, const T *, T *, const int *, \
                                   hipStream_t);                                                     \
   template void launch_copy_t<T>(int64_t, const T *, T *, const int *, hipStream_t);                \

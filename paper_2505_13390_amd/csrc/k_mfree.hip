@@ -192,6 +192,27 @@ void launch_mf_cheb(const MfView<T> &A, const T *r, const T *dinv, const T *coef
                     nullptr, s);
 }
 template <class T>
+void launch_mf_jacobi_prolong(const MfView<T> &A, const T *wdinv, const T *r, const T *zi,
+                              const T *p, const int32_t *agg, const T *e, T *zo,
+                              const int *done, hipStream_t s) {
+  const InProlong<T> in{zi, p, e, agg};
+  launch_mf_pass<T>(A, in, OpJacobi<T, InProlong<T>>{wdinv, r, in, zo}, done, nullptr, s);
+}
+template <class T>
+void launch_mf_cheb_prolong(const MfView<T> &A, const T *r, const T *dinv, const T *coef,
+                            const int32_t *rowseg, int steps, int k, const T *zi, const T *p,
+                            const int32_t *agg, const T *e, T *d, T *zo, const int *done,
+                            hipStream_t s) {
+  const InProlong<T> in{zi, p, e, agg};
+  launch_mf_pass<T>(A, in, OpCheb<T, InProlong<T>>{r, dinv, d, zo, coef, rowseg, steps, k, in},
+                    done, nullptr, s);
+}
+template <class T>
+void launch_mf_residual_scaled(const MfView<T> &A, const T *r, const T *z, const T *p, T *w,
+                               const int *done, hipStream_t s) {
+  launch_mf_pass<T>(A, InVec<T>{z}, OpResidualScaled<T>{r, p, w}, done, nullptr, s);
+}
+template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s) {
   launch_mf_pass<T>(A, InVec<T>{z}, OpResidual<T>{r, res}, done, nullptr, s);
@@ -212,6 +233,15 @@ int launch_mf_rows_dot(const MfView<double> &A, const double *p, double *q, cons
   template void launch_mf_prepare<T>(int64_t, const double *, const double *, const double *,  \
                                      int64_t, const int32_t *, const int8_t *, const double *,  \
                                      T *, T *, hipStream_t);                                    \
+  template void launch_mf_jacobi_prolong<T>(const MfView<T> &, const T *, const T *, const T *, \
+                                            const T *, const int32_t *, const T *, T *,         \
+                                            const int *, hipStream_t);                          \
+  template void launch_mf_cheb_prolong<T>(const MfView<T> &, const T *, const T *, const T *,   \
+                                          const int32_t *, int, int, const T *, const T *,      \
+                                          const int32_t *, const T *, T *, T *, const int *,    \
+                                          hipStream_t);                                         \
+  template void launch_mf_residual_scaled<T>(const MfView<T> &, const T *, const T *, const T *, \
+                                             T *, const int *, hipStream_t);                     \
   template void launch_mf_jacobi<T>(const MfView<T> &, const T *, const T *, const T *, T *,    \
                                     const int *, hipStream_t);                                  \
   template void launch_mf_residual<T>(const MfView<T> &, const T *, const T *, T *,             \

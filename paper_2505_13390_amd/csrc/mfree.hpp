@@ -52,9 +52,24 @@ template <class T>
 void launch_mf_cheb(const MfView<T> &A, const T *r, const T *dinv, const T *coef,
                     const int32_t *rowseg, int steps, int k, const T *zi, T *d, T *zo,
                     const int *done, hipStream_t s);
+// the first post-smoothing step with the coarse correction z + P e formed
+// on the fly (see launch_jacobi_prolong)
+template <class T>
+void launch_mf_jacobi_prolong(const MfView<T> &A, const T *wdinv, const T *r, const T *zi,
+                              const T *p, const int32_t *agg, const T *e, T *zo,
+                              const int *done, hipStream_t s);
+template <class T>
+void launch_mf_cheb_prolong(const MfView<T> &A, const T *r, const T *dinv, const T *coef,
+                            const int32_t *rowseg, int steps, int k, const T *zi, const T *p,
+                            const int32_t *agg, const T *e, T *d, T *zo, const int *done,
+                            hipStream_t s);
 template <class T>
 void launch_mf_residual(const MfView<T> &A, const T *r, const T *z, T *res, const int *done,
                         hipStream_t s);
+// w = p (r - A z), the terms of the restriction P^T (r - A z) in row order
+template <class T>
+void launch_mf_residual_scaled(const MfView<T> &A, const T *r, const T *z, const T *p, T *w,
+                               const int *done, hipStream_t s);
 // the PCG product q = A p as its two kernels (timed one by one when
 // profiling): the vertex gather, then the row pass writing q and the partial
 // sums of p^T q (returns the number of partials; launch_fin_pq finishes)

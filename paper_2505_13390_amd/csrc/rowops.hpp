@@ -26,6 +26,15 @@ struct InScaled {  // the first sweep from z = 0: z_j = omega D^-1 r, as r_j * w
   const T *r, *wdinv;
   __device__ __forceinline__ T operator()(int64_t j) const { return r[j] * wdinv[j]; }
 };
+template <class T>
+struct InProlong {  // the iterate after the coarse correction: z_j + p_j e_agg(j)
+  const T *z, *p, *e;
+  const int32_t *agg;   // -1: row not aggregated (isolated), no correction
+  __device__ __forceinline__ T operator()(int64_t j) const {
+    const int32_t a = agg[j];
+    return a >= 0 ? z[j] + p[j] * e[a] : z[j];
+  }
+};
 template <class T, class In>
 struct OpJacobi {  // zo = zi + omega D^-1 (r - A zi), wdinv = omega D^-1 per row
   const T *wdinv, *r;
@@ -55,6 +64,12 @@ struct OpCheb {
   }
 };
 
+template <class T>
+struct OpResidualScaled {  // w = p (r - A z): the restriction's terms, stored in row order
+  const T *r, *p;
+  T *w;
+  __device__ void operator()(int64_t i, T s, double &) const { w[i] = p[i] * (r[i] - s); }
+};
 template <class T>
 struct OpResidual {  // res = r - A z
   const T *r;

@@ -33,6 +33,7 @@ Solver::Solver(const mgpbd_options &o) : opt(o) {
 Solver::~Solver() {
   invalidate_graph();
   for (auto e : ev) (void)hipEventDestroy(e);
+  for (auto e : lev_ev) (void)hipEventDestroy(e);
   if (pinned) (void)hipHostFree(pinned);
 }
 
@@ -47,6 +48,19 @@ void Solver::ensure_pinned(size_t bytes) {
 
 void Solver::ensure_partials(int nblk) {
   red_partials.reserve(kMaxBlockSums * (size_t)std::max(nblk, kMaxGrid) + 64);
+}
+
+void Solver::reset_profile() {
+  spmv_calls = 0;
+  spmv_ms = 0.0;
+  spmv_first_ms = 0.0;
+  vcycles = 0;
+  for (double &v : level_ms) v = 0.0;
+}
+
+void Solver::pmark(int l, int j) {
+  if (prof_k < 0 || l >= kProfLevels) return;
+  MG_HIP(hipEventRecord(lev_ev[((size_t)prof_k * kProfLevels + l) * 4 + j], st));
 }
 
 void Solver::set_stream(hipStream_t s) {
@@ -124,6 +138,7 @@ void Solver::finish_level(int l) {
     L.r.alloc(L.n); L.t.alloc(L.n);
     if (mixed()) { L.r32.alloc(L.n); L.t32.alloc(L.n); }
     tune_lanes(l);
+    if (l == 0 && opt.matrix_free == 2 && mf.ok()) choose_fine_operator();
   }
   L.diag.alloc(L.n);
   L.dinv.alloc(L.n);
@@ -140,6 +155,7 @@ void Solver::finish_level(int l) {
   if (mixed()) { L.r32.alloc(L.n); L.z32.alloc(L.n); L.t32.alloc(L.n); }
   L.res.alloc(L.n);
   if (mixed()) L.res32.alloc(L.n);
+  sync_sell_level(l);   // the products below read the level's SELL copy when it has one
   power_omega(l);
   if (opt.smoother == 1) chebyshev_table(l);
   if (opt.smoother == 2) colour_level(l);
@@ -155,6 +171,7 @@ void Solver::tune_lanes(int l) {
   Level &L = *lev[l];
   L.tile = L.tile32 = 0;
   L.nt = L.nt32 = false;
+  L.sell = L.sell32 = false;
   if (opt.spmv_lanes > 0) L.lanes = L.lanes32 = opt.spmv_lanes;
   if (opt.spmv_tile > 0 && L.n > 0) {
     std::vector<int64_t> hrp(L.n + 1), part;
@@ -169,18 +186,31 @@ void Solver::tune_lanes(int l) {
     }
     return;
   }
+  if (opt.spmv_tile == -2 && L.n > 0) {   // SELL-C-sigma on every level
+    std::vector<int64_t> hrp(L.n + 1);
+    L.rowptr.download(hrp.data(), L.n + 1, st);
+    MG_HIP(hipStreamSynchronize(st));
+    build_sell_level(l, hrp);
+    L.sell = true;
+    L.sell32 = mixed() && L.sell_val32.p;
+    MG_HIP(hipStreamSynchronize(st));
+    return;
+  }
   if (opt.spmv_tile < 0 || opt.spmv_lanes > 0 || L.n < 20000) return;
   std::vector<int64_t> hrp(L.n + 1);
   L.rowptr.download(hrp.data(), L.n + 1, st);
   MG_HIP(hipStreamSynchronize(st));
-  struct Cand { int lanes, tile; bool nt; std::vector<int64_t> part; };
+  struct Cand { int lanes, tile; bool nt; std::vector<int64_t> part; bool sell; };
   std::vector<Cand> cands;
-  for (int g : {8, 16, 32, 64}) cands.push_back({g, 0, false, {}});
+  for (int g : {8, 16, 32, 64}) cands.push_back({g, 0, false, {}, false});
   for (int t : {1024, 2048, 4096})
     for (bool ntl : {false, true}) {
-      Cand c{16, t, ntl, {}};
+      Cand c{16, t, ntl, {}, false};
       if (build_row_tiles(hrp, t, c.part)) cands.push_back(std::move(c));
     }
+  // the SELL-C-sigma copy of this level, timed like the CSR variants
+  build_sell_level(l, hrp);
+  cands.push_back({0, 0, false, {}, true});
   hipEvent_t a, b;
   MG_HIP(hipEventCreate(&a));
   MG_HIP(hipEventCreate(&b));
@@ -207,11 +237,14 @@ void Solver::tune_lanes(int l) {
     A.lanes = c.lanes; A.tile = c.tile; A.nt = c.nt;
     A.ntiles = c.tile ? (int64_t)c.part.size() - 1 : 0;
     A.tiles = c.tile ? tmp.p : nullptr;
+    if (c.sell) A.sell = {L.sell_chunks, L.sell_perm.p, L.sell_ptr.p, L.sell_col.p, L.sell_val.p};
     float ms = timeit([&] { launch_spmv<double>(A, L.r.p, L.t.p, st); });
     if (ms < best) { best = ms; pick = k; }
     if (do32) {
       CsrView<float> F = L.view32();
       F.lanes = c.lanes; F.tile = c.tile; F.nt = c.nt; F.ntiles = A.ntiles; F.tiles = A.tiles;
+      if (c.sell)
+        F.sell = {L.sell_chunks, L.sell_perm.p, L.sell_ptr.p, L.sell_col.p, L.sell_val32.p};
       float ms32 = timeit([&] { launch_spmv<float>(F, L.r32.p, L.t32.p, st); });
       if (ms32 < best32) { best32 = ms32; pick32 = k; }
     }
@@ -220,7 +253,10 @@ void Solver::tune_lanes(int l) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   const Cand &c = cands[pick];
-  L.lanes = c.lanes;
+  L.sell = c.sell;
+  L.sell32 = do32 && cands[pick32].sell;
+  if (c.sell) L.lanes = lanes_for_rowlen(L.n ? (double)L.nnz / (double)L.n : 1.0);
+  else L.lanes = c.lanes;
   L.tile = c.tile;
   L.nt = c.nt;
   if (c.tile) {
@@ -229,7 +265,7 @@ void Solver::tune_lanes(int l) {
   }
   if (do32) {
     const Cand &c32 = cands[pick32];
-    L.lanes32 = c32.lanes;
+    L.lanes32 = c32.sell ? lanes_for_rowlen(L.n ? (double)L.nnz / (double)L.n : 1.0) : c32.lanes;
     L.tile32 = c32.tile;
     L.nt32 = c32.nt;
     if (c32.tile) {
@@ -237,7 +273,56 @@ void Solver::tune_lanes(int l) {
       L.ntiles32 = (int64_t)c32.part.size() - 1;
     }
   }
+  if (!L.sell) L.sell_val.release();
+  if (!L.sell32) L.sell_val32.release();
+  if (!L.sell && !L.sell32) {
+    L.sell_perm.release();
+    L.sell_ptr.release();
+    L.sell_col.release();
+    L.sell_slot.release();
+    L.sell_chunks = 0;
+  }
   MG_HIP(hipStreamSynchronize(st));
+}
+
+// SELL-C-sigma layout of level l (host build from its pattern) with the
+// level's current values (FP32 as well in the mixed path)
+void Solver::build_sell_level(int l, const std::vector<int64_t> &hrp) {
+  Level &L = *lev[l];
+  std::vector<int32_t> hcol(L.nnz), perm, scol;
+  std::vector<int64_t> ptr, slot;
+  L.col.download(hcol.data(), L.nnz, st);
+  MG_HIP(hipStreamSynchronize(st));
+  build_sell(hrp, hcol, perm, ptr, scol, slot);
+  L.sell_chunks = (int64_t)ptr.size() - 1;
+  L.sell_perm.upload(perm.data(), perm.size(), st);
+  L.sell_ptr.upload(ptr.data(), ptr.size(), st);
+  L.sell_col.upload(scol.data(), scol.size(), st);   // non-empty: every row has its diagonal
+  L.sell_slot.upload(slot.data(), slot.size(), st);
+  L.sell_val.alloc(std::max<size_t>(scol.size(), 1));
+  MG_HIP(hipMemsetAsync(L.sell_val.p, 0, sizeof(double) * L.sell_val.n, st));
+  launch_sell_values<double, double>(L.nnz, L.sell_slot.p, L.val.p, L.sell_val.p, st);
+  if (mixed() && L.val32.p) {
+    L.sell_val32.alloc(std::max<size_t>(scol.size(), 1));
+    MG_HIP(hipMemsetAsync(L.sell_val32.p, 0, sizeof(float) * L.sell_val32.n, st));
+    launch_sell_values<float, float>(L.nnz, L.sell_slot.p, L.val32.p, L.sell_val32.p, st);
+  }
+  MG_HIP(hipStreamSynchronize(st));
+}
+
+void Solver::sync_sell_level(int l) {
+  Level &L = *lev[l];
+  if (L.sell) launch_sell_values<double, double>(L.nnz, L.sell_slot.p, L.val.p, L.sell_val.p, st);
+  if (L.sell32) {
+    if (L.val32.p)
+      launch_sell_values<float, float>(L.nnz, L.sell_slot.p, L.val32.p, L.sell_val32.p, st);
+    else
+      launch_sell_values<double, float>(L.nnz, L.sell_slot.p, L.val.p, L.sell_val32.p, st);
+  }
+}
+
+void Solver::sync_sell() {
+  for (int l = 0; l < nlev; ++l) sync_sell_level(l);
 }
 
 // omega = 2 / (lmax_scale lambda_max(D^-1 A) + lambda_min) for each body,
@@ -750,6 +835,8 @@ void Solver::factor_dense() {
 void Solver::setup() {
   invalidate_graph();
   built = false;
+  tail_l0 = 0;
+  tail_nb = 0;
   while (lev.size() > 1) lev.pop_back();
   Level &F = *lev[0];
   if (F.seg.empty() || F.seg.back() != F.n) set_bodies({0, F.n});
@@ -825,7 +912,128 @@ void Solver::setup() {
   plan_dense();
   factor_dense();
   ensure_vectors();
+  plan_tail();
+  sync_sell();
   built = true;
+}
+
+// matrix_free = 2: one FP64 fine-level product timed both ways on the first
+// setup (the constraint-gradient operator, and the assembled values in the
+// format the autotuner picked for level 0); when the assembled form is faster
+// the matrix-free views are dropped, so every fine-level pass of this context
+// (PCG product, smoothing, residual, in both precisions) reads the assembled
+// values from then on. For a batch the choice covers the whole system.
+void Solver::choose_fine_operator() {
+  Level &F = *lev[0];
+  launch_fill(F.n, 1.0, F.r.p, st);
+  hipEvent_t a, b;
+  MG_HIP(hipEventCreate(&a));
+  MG_HIP(hipEventCreate(&b));
+  auto timeit = [&](auto &&fn) {
+    fn();   // warm
+    MG_HIP(hipEventRecord(a, st));
+    for (int rep = 0; rep < 3; ++rep) fn();
+    MG_HIP(hipEventRecord(b, st));
+    MG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    MG_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  };
+  const float t_mf = timeit([&] {
+    launch_mf_gather(mf, F.r.p, nullptr, st);
+    launch_mf_rows_dot(mf, F.r.p, F.t.p, nullptr, nullptr, st);
+  });
+  const float t_csr = timeit([&] { launch_spmv<double>(F.view(), F.r.p, F.t.p, st); });
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (t_csr < t_mf) {
+    mf = MfView<double>();
+    mf32 = MfView<float>();
+  }
+}
+
+// The fused coarse V-cycle starts at the first level l >= 1 from which on
+// every body has at most opt.vcycle_tail rows per level, provided each body
+// there ends in a dense solve, the transfers are one-column (K = 1), the
+// smoother is Jacobi or Chebyshev and the bodies' depth below fits the table.
+void Solver::plan_tail() {
+  tail_l0 = 0;
+  tail_nb = 0;
+  if (opt.vcycle_tail <= 0 || opt.smoother == 2 || nlev < 2) return;
+  int l0 = nlev;
+  for (int l = nlev - 1; l >= 1; --l) {
+    const Level &L = *lev[l];
+    bool small = L.K == 1 || l == nlev - 1;
+    for (size_t k = 0; small && k + 1 < L.seg.size(); ++k)
+      small = L.seg[k + 1] - L.seg[k] <= (int64_t)opt.vcycle_tail;
+    if (!small) break;
+    l0 = l;
+  }
+  if (l0 >= nlev || nlev - l0 > kTailMaxDepth) return;
+  const Level &S = *lev[l0];
+  std::vector<TailBody> tb;
+  for (int s0 = 0; s0 + 1 < (int)S.seg.size(); ++s0) {
+    if (S.seg[s0 + 1] == S.seg[s0]) continue;   // no rows: nothing to do
+    TailBody b;
+    const int body = S.body[s0];
+    int seg = s0;
+    for (int l = l0;; ++l) {
+      const Level &L = *lev[l];
+      b.row0[l - l0] = L.seg[seg];
+      b.n[l - l0] = L.seg[seg + 1] - L.seg[seg];
+      b.depth = l - l0 + 1;
+      if (l == nlev - 1 || L.terminal[seg]) {
+        const DenseJob *job = nullptr;
+        for (const DenseJob &j : L.jobs)
+          if (j.row0 == L.seg[seg] && j.n == b.n[l - l0]) job = &j;
+        if (!job) return;   // a last level without a dense solve: keep the per-level path
+        b.ainv = job->ainv;
+        break;
+      }
+      const Level &C = *lev[l + 1];
+      int next = -1;
+      for (size_t k = 0; k < C.body.size(); ++k)
+        if (C.body[k] == body) next = (int)k;
+      if (next < 0) return;
+      seg = next;
+    }
+    tb.push_back(b);
+  }
+  if (tb.empty()) return;
+  std::vector<TailLevel<double>> v64;
+  std::vector<TailLevel<float>> v32;
+  for (int l = l0; l < nlev; ++l) {
+    Level &L = *lev[l];
+    TailLevel<double> d;
+    d.rp = L.rowptr.p; d.col = L.col.p; d.val = L.val.p;
+    d.wdinv = L.wdinv.p; d.dinv = L.dinv.p; d.cheb = L.cheb.p; d.rowseg = L.rowseg.p;
+    d.G = L.tile > 0 ? 8 : L.lanes;   // the stream kernels sum rows with 8 lanes
+    d.rlanes = L.rlanes;
+    d.p = L.p.p; d.agg = L.agg.p; d.agg_ptr = L.agg_ptr.p; d.agg_mem = L.agg_mem.p;
+    d.r = L.r.p; d.z = L.z.p; d.t = L.t.p; d.res = L.res.p; d.dir = L.dir.p;
+    v64.push_back(d);
+    if (mixed()) {
+      TailLevel<float> f;
+      f.rp = L.rowptr.p; f.col = L.col.p; f.val = L.val32.p;
+      f.wdinv = L.wdinv32.p; f.dinv = L.dinv32.p; f.cheb = L.cheb32.p; f.rowseg = L.rowseg.p;
+      f.G = L.tile32 > 0 ? 8 : L.lanes32;
+      f.rlanes = L.rlanes;
+      f.p = L.p32.p; f.agg = L.agg.p; f.agg_ptr = L.agg_ptr.p; f.agg_mem = L.agg_mem.p;
+      f.r = L.r32.p; f.z = L.z32.p; f.t = L.t32.p; f.res = L.res32.p; f.dir = L.dir32.p;
+      v32.push_back(f);
+    }
+  }
+  tail_lv.upload(v64.data(), v64.size(), st);
+  if (mixed()) tail_lv32.upload(v32.data(), v32.size(), st);
+  tail_bodies.upload(tb.data(), tb.size(), st);
+  tail_plan.pre = opt.pre_sweeps;
+  tail_plan.post = opt.post_sweeps;
+  tail_plan.smoother = opt.smoother;
+  tail_plan.steps = std::max(1, std::max(opt.pre_sweeps, opt.post_sweeps));
+  tail_plan.fuse_first = opt.smoother == 0;
+  MG_HIP(hipStreamSynchronize(st));
+  tail_nb = (int)tb.size();
+  tail_l0 = l0;
 }
 
 void Solver::refresh() {
@@ -843,6 +1051,7 @@ void Solver::refresh() {
   }
   MG_REQUIRE(read_flag(kFBadDiag) == 0, MGPBD_E_BREAKDOWN, "non-positive diagonal entry");
   factor_dense();
+  sync_sell();
 }
 
 void Solver::ensure_vectors() {
@@ -856,6 +1065,7 @@ void Solver::ensure_vectors() {
 // ------------------------------------------------------------ V-cycle
 template <class T> struct Buf;
 template <> struct Buf<double> {
+  static const TailLevel<double> *tail(const Solver &S) { return S.tail_lv.p; }
   static DevBuf<double> &z(Level &L) { return L.z; }
   static DevBuf<double> &t(Level &L) { return L.t; }
   static DevBuf<double> &r(Level &L) { return L.r; }
@@ -869,6 +1079,7 @@ template <> struct Buf<double> {
   static const double *Q(const Level &L) { return L.Q.p; }
 };
 template <> struct Buf<float> {
+  static const TailLevel<float> *tail(const Solver &S) { return S.tail_lv32.p; }
   static DevBuf<float> &z(Level &L) { return L.z32; }
   static DevBuf<float> &t(Level &L) { return L.t32; }
   static DevBuf<float> &r(Level &L) { return L.r32; }
@@ -909,6 +1120,7 @@ void Solver::gs_vcycle(int l, const T *r, T *z) {
                        dv, r, z, done, st);
     }
   };
+  pmark(l, 0);
   launch_zero_t<T>(L.n, z, done, st);
   for (int k = 0; k < opt.pre_sweeps; ++k) sweep(false);
   if (l + 1 < nlev) {
@@ -920,13 +1132,19 @@ void Solver::gs_vcycle(int l, const T *r, T *z) {
     else launch_residual<T>(A, r, z, res, done, st);
     (void)pl;
     restrict_to<T>(l, res, rc);
+    pmark(l, 1);
     vcycle<T>(l + 1, rc, ec);
+    pmark(l, 2);
     prolong_from<T>(l, ec, z);
+  } else {
+    pmark(l, 1);
+    pmark(l, 2);
   }
   for (int k = 0; k < opt.post_sweeps; ++k) sweep(true);
   if (!L.jobs.empty())
     launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
                                 Ainv.p, r, z, done, st);
+  pmark(l, 3);
 }
 
 // transfers between level l and l + 1: P^T (restriction) and P (prolongation
@@ -956,9 +1174,22 @@ template <class T>
 void Solver::vcycle(int l, const T *r, T *z) {
   Level &L = *lev[l];
   const int *done = done_ptr();
+  if (tail_l0 > 0 && l == tail_l0) {   // every coarser level in one launch
+    pmark(l, 0);
+    launch_vcycle_tail<T>(tail_nb, Buf<T>::tail(*this), tail_bodies.p, tail_plan, Ainv.p, done,
+                          st);
+    pmark(l, 1);
+    pmark(l, 2);
+    pmark(l, 3);
+    return;
+  }
   if (!L.smooth_here) {   // every body on this level ends with a dense solve
+    pmark(l, 0);
     launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
                                 Ainv.p, r, z, done, st);
+    pmark(l, 1);
+    pmark(l, 2);
+    pmark(l, 3);
     return;
   }
   const int pre = opt.pre_sweeps, post = opt.post_sweeps;
@@ -997,6 +1228,7 @@ void Solver::vcycle(int l, const T *r, T *z) {
     gs_vcycle<T>(l, r, z);
     return;
   }
+  pmark(l, 0);
   T *cur = next();
   int k0 = 1;
   if (pre == 0) {
@@ -1015,21 +1247,61 @@ void Solver::vcycle(int l, const T *r, T *z) {
     sweep(k, cur, o);
     cur = o;
   }
+  // With fuse_transfers (off by default: measured slower) and a one-column
+  // transfer (K = 1): on assembled levels the residual and the restriction
+  // are one pass, and on every level the prolongation is folded into the
+  // first post-sweep, which reads z + P e through its input functor instead
+  // of a stored z.
+  const bool fold = coarse && opt.fuse_transfers && L.K == 1 && post > 0;
+  const T *ec_fold = nullptr;
   if (coarse) {
     Level &C = *lev[l + 1];
     T *rc = Buf<T>::r(C).p, *ec = Buf<T>::z(C).p;
     const T *pl = Buf<T>::p(L);
     T *res = Buf<T>::res(L).p;
-    if (M) launch_mf_residual<T>(*M, r, cur, res, done, st);
-    else launch_residual<T>(A, r, cur, res, done, st);
-    (void)pl;
-    restrict_to<T>(l, res, rc);
+    if (!M && opt.fuse_transfers && L.K == 1) {
+      launch_residual_restrict<T>(A, r, cur, C.n, L.agg_ptr.p, L.agg_mem.p, pl, rc, done, st);
+    } else if (M && L.K == 1) {
+      // the matrix-free residual stores the restriction's terms p_i res_i in
+      // row order (coalesced), so the restriction gathers one scattered value
+      // per member instead of two; the terms and their order are unchanged
+      launch_mf_residual_scaled<T>(*M, r, cur, pl, res, done, st);
+      launch_restrict_sum<T>(C.n, L.agg_ptr.p, L.agg_mem.p, res, rc, L.rlanes, done, st);
+    } else {
+      if (M) launch_mf_residual<T>(*M, r, cur, res, done, st);
+      else launch_residual<T>(A, r, cur, res, done, st);
+      restrict_to<T>(l, res, rc);
+    }
+    pmark(l, 1);
     vcycle<T>(l + 1, rc, ec);
-    prolong_from<T>(l, ec, cur);
+    pmark(l, 2);
+    if (fold) ec_fold = ec;
+    else prolong_from<T>(l, ec, cur);
+  } else {
+    pmark(l, 1);
+    pmark(l, 2);
   }
   for (int k = 0; k < post; ++k) {
     T *o = next();
-    sweep(k, cur, o);
+    if (k == 0 && fold) {
+      const T *pl = Buf<T>::p(L);
+      if (cheb) {
+        const T *dv = Buf<T>::dinv(L), *cf = Buf<T>::cheb(L);
+        T *d = Buf<T>::dir(L);
+        if (M)
+          launch_mf_cheb_prolong<T>(*M, r, dv, cf, L.rowseg.p, steps, 0, cur, pl, L.agg.p,
+                                    ec_fold, d, o, done, st);
+        else
+          launch_cheb_prolong<T>(A, r, dv, cf, L.rowseg.p, steps, 0, cur, pl, L.agg.p, ec_fold,
+                                 d, o, done, st);
+      } else if (M) {
+        launch_mf_jacobi_prolong<T>(*M, wd, r, cur, pl, L.agg.p, ec_fold, o, done, st);
+      } else {
+        launch_jacobi_prolong<T>(A, wd, r, cur, pl, L.agg.p, ec_fold, o, done, st);
+      }
+    } else {
+      sweep(k, cur, o);
+    }
     cur = o;
   }
   if (cur != z) launch_copy_t<T>(L.n, cur, z, done, st);   // not reached: w makes cur == z
@@ -1037,6 +1309,7 @@ void Solver::vcycle(int l, const T *r, T *z) {
   if (!L.jobs.empty())
     launch_dense_apply_batch<T>((int)L.jobs.size(), L.d_jobs.p, L.job_rows, L.d_jobstart.p,
                                 Ainv.p, r, z, done, st);
+  pmark(l, 3);
 }
 
 // ------------------------------------------------------------ PCG
@@ -1076,6 +1349,7 @@ void Solver::iterate_once(int k) {
   }
   if (nb > 1) launch_s_pcg_dot_pq(t, ctl.p, p.p, q.p, partials(), st);
   launch_s_pcg_update(t, ctl.p, p.p, q.p, x.p, r.p, partials(), all_done.p, st);
+  prof_k = opt.profile_spmv ? k : -1;
   if (flex) {
     launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
     vcycle<float>(0, F.r32.p, F.z32.p);
@@ -1084,6 +1358,7 @@ void Solver::iterate_once(int k) {
     vcycle<double>(0, r.p, z.p);
     launch_s_pcg_rz(t, ctl.p, r.p, z.p, nullptr, zold.p, false, partials(), all_done.p, st);
   }
+  prof_k = -1;
   launch_s_pcg_pupdate(t, ctl.p, z.p, p.p, st);
 }
 
@@ -1149,6 +1424,9 @@ std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, i
     for (auto e : ev) (void)hipEventDestroy(e);
     ev.assign(3 * chunk, nullptr);
     for (auto &e : ev) MG_HIP(hipEventCreate(&e));
+    for (auto e : lev_ev) (void)hipEventDestroy(e);
+    lev_ev.assign((size_t)chunk * kProfLevels * 4, nullptr);
+    for (auto &e : lev_ev) MG_HIP(hipEventCreate(&e));
   }
   if (use_graph && !graph_ok) {
     invalidate_graph();
@@ -1196,6 +1474,16 @@ std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, i
         spmv_ms += ms;
         spmv_first_ms += ms1;
         ++spmv_calls;
+        // levels below the start of the fused tail record no events of their own
+        const int visited = tail_l0 > 0 ? tail_l0 + 1 : nlev;
+        for (int l = 0; l < std::min(visited, (int)kProfLevels); ++l) {
+          hipEvent_t *e = &lev_ev[((size_t)k * kProfLevels + l) * 4];
+          float a = 0.f, b = 0.f;
+          MG_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+          MG_HIP(hipEventElapsedTime(&b, e[2], e[3]));
+          level_ms[l] += a + b;
+        }
+        ++vcycles;
       }
     }
   }

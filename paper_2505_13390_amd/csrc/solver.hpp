@@ -12,6 +12,7 @@
 #include "mfree.hpp"
 #include "seg.hpp"
 #include "setup.hpp"
+#include "tail.hpp"
 
 namespace mgpbd {
 
@@ -23,6 +24,14 @@ struct Level {
   bool nt = false, nt32 = false;  // non-temporal matrix loads in the stream kernels
   DevBuf<int64_t> tiles, tiles32;
   int64_t ntiles = 0, ntiles32 = 0;
+  // SELL-C-sigma copy when the autotuner picks it (sell / sell32): layout,
+  // and the slot of every CSR entry for refreshing its values
+  bool sell = false, sell32 = false;
+  int64_t sell_chunks = 0;
+  DevBuf<int32_t> sell_perm, sell_col;
+  DevBuf<int64_t> sell_ptr, sell_slot;
+  DevBuf<double> sell_val;
+  DevBuf<float> sell_val32;
   DevBuf<int64_t> rowptr;
   DevBuf<int32_t> col;
   DevBuf<double> val;
@@ -85,12 +94,14 @@ struct Level {
     CsrView<double> v;
     v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val.p; v.lanes = lanes;
     v.tile = tile; v.nt = nt; v.ntiles = ntiles; v.tiles = tiles.p;
+    if (sell) v.sell = {sell_chunks, sell_perm.p, sell_ptr.p, sell_col.p, sell_val.p};
     return v;
   }
   CsrView<float> view32() const {
     CsrView<float> v;
     v.n = n; v.nnz = nnz; v.rowptr = rowptr.p; v.col = col.p; v.val = val32.p; v.lanes = lanes32;
     v.tile = tile32; v.nt = nt32; v.ntiles = ntiles32; v.tiles = tiles32.p;
+    if (sell32) v.sell = {sell_chunks, sell_perm.p, sell_ptr.p, sell_col.p, sell_val32.p};
     return v;
   }
 };
@@ -125,6 +136,25 @@ class Solver {
   int64_t spmv_calls = 0;
   double spmv_ms = 0.0;        // whole product (both kernels when matrix-free)
   double spmv_first_ms = 0.0;  // its first kernel (the matrix-free gather; 0 for CSR)
+  // profiling of the V-cycle level by level: each level's own passes (entry to
+  // descent plus return to exit) summed over the timed V-cycles
+  static constexpr int kProfLevels = 16;
+  // fused coarse end of the V-cycle (tail.hpp): start level (0 = not used),
+  // bodies present there, per-level views in both precisions, per-body rows
+  int tail_l0 = 0;
+  int tail_nb = 0;
+  TailPlan tail_plan;
+  DevBuf<TailLevel<double>> tail_lv;
+  DevBuf<TailLevel<float>> tail_lv32;
+  DevBuf<TailBody> tail_bodies;
+  void plan_tail();
+  void choose_fine_operator();   // matrix_free = 2: keep the faster fine-level product
+  void sync_sell();   // SELL copies take the levels' current values
+  void sync_sell_level(int l);
+  void build_sell_level(int l, const std::vector<int64_t> &hrp);
+  double level_ms[kProfLevels] = {};
+  int64_t vcycles = 0;
+  void reset_profile();
 
   Level &L0() { return *lev[0]; }
   bool mixed() const { return opt.precision == MGPBD_PREC_MIXED; }
@@ -174,6 +204,11 @@ class Solver {
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   std::vector<hipEvent_t> ev;
+  // level events of the profiled V-cycles: [chunk slot][level][4] (entry,
+  // descent, return, exit); prof_k = slot of the V-cycle being recorded
+  std::vector<hipEvent_t> lev_ev;
+  int prof_k = -1;
+  void pmark(int l, int j);
 
   double *partials() { return red_partials.p; }
   const int *done_ptr() const;

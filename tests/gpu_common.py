@@ -21,10 +21,12 @@ def log(*a):
 
 def opts(**kw):
     """Matching (oracle, gpu) options; gpu-only keys: precision, use_graph,
-    check_every, profile_spmv, spmv_tile, spmv_lanes, matrix_free."""
+    check_every, profile_spmv, spmv_tile, spmv_lanes, matrix_free, vcycle_tail,
+    fuse_transfers."""
     gkw = {k: kw.pop(k) for k in list(kw) if k in ("precision", "use_graph", "check_every",
                                                    "profile_spmv", "spmv_tile", "spmv_lanes",
-                                                   "matrix_free")}
+                                                   "matrix_free", "vcycle_tail",
+                                                   "fuse_transfers")}
     o = O.default_opts(**kw)
     if gkw.get("precision", 0) == B.PREC_MIXED:
         o.flexible = 1

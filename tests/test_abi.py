@@ -50,6 +50,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.smoother == 0
     assert o.n_cand == 1
     assert o.power_max == 500 and o.power_tol == 1e-2
+    assert o.vcycle_tail == 0 and o.fuse_transfers == 0
 
 
 def test_null_arguments_rejected_without_device_work():
@@ -75,3 +76,35 @@ def test_binding_rejects_host_and_short_tensors_before_calling_the_library():
         binding._vec(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "x")
     with pytest.raises(TypeError):
         binding._dev([0.0, 1.0])
+
+
+def test_struct_offsets_match_the_header(tmp_path):
+    """Every field offset and size of the option and statistics structs as a C
+    compiler lays them out from include/mgpbd.h, against the binding's ctypes
+    structs."""
+    import shutil
+    import subprocess
+    from paper_2505_13390_amd import binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mgpbd_options": binding.Options, "mgpbd_step_stats": binding.StepStats,
+               "mgpbd_solve_stats": binding.SolveStats, "mgpbd_mesh": binding.Mesh,
+               "mgpbd_constraints": binding.Constraints, "mgpbd_csr": binding.Csr}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mgpbd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                           str(src)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)]).decode().split("\n")
+               if l)
+    for cname, py in structs.items():
+        assert int(got["%s size" % cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)

@@ -160,10 +160,12 @@ def test_c0_frame_with_forced_pcg_counts():
     assert err <= 1e-9
 
 
-@pytest.mark.parametrize("tile,lanes", [(1024, 0), (2048, 0), (4096, 0), (-1, 4), (-1, 64)])
+@pytest.mark.parametrize("tile,lanes", [(1024, 0), (2048, 0), (4096, 0), (-1, 4), (-1, 64),
+                                        (-2, 0)])
 def test_csr_pass_variants_match_oracle(tile, lanes):
-    """Every CSR product variant the autotuner may pick (LDS stream tiles and
-    lanes-per-row counts) gives oracle parity on the 8x8x32 beam."""
+    """Every CSR product variant the autotuner may pick (LDS stream tiles,
+    lanes-per-row counts, SELL-C-sigma with tile -2) gives oracle parity on the
+    8x8x32 beam."""
     w = W.beam_c0()
     sim, body, pos, vel, ores, gres = run_both(w, 3, spmv_tile=tile, spmv_lanes=lanes,
                                                matrix_free=0)
@@ -284,10 +286,13 @@ def test_solve_rejects_malformed_csr():
     B.mgpbd_destroy(ctx)
 
 
-@pytest.mark.parametrize("mf", [1, 0])
-def test_mixed_precision_against_fp64_oracle(mf):
+@pytest.mark.parametrize("mf,tile", [(1, 0), (0, 0), (0, -2), (2, 0)])
+def test_mixed_precision_against_fp64_oracle(mf, tile):
+    """FP32 V-cycle against the FP64 oracle: matrix-free, assembled or timed
+    choice (mf 2) of the fine-level operator, and every level in the
+    SELL-C-sigma format (tile -2)."""
     w = W.beam_c0()
-    oo, go = opts(precision=B.PREC_MIXED, matrix_free=mf)
+    oo, go = opts(precision=B.PREC_MIXED, matrix_free=mf, spmv_tile=tile)
     oo64, _ = opts()
     sim = O.Sim(w, oo64)
     pos, vel = O.positions(w)
@@ -569,3 +574,22 @@ def test_failed_frame_leaves_positions_and_velocities_unchanged():
     for b, x, v in zip(batch.bodies, xs, vs):
         assert np.array_equal(b.positions(), x) and np.array_equal(b.velocities(), v)
     batch.close()
+
+
+@pytest.mark.parametrize("fuse,mf,smoother", [(1, 1, 0), (0, 1, 0), (1, 0, 0), (0, 0, 0),
+                                              (1, 1, 1), (1, 0, 1)])
+def test_transfer_forms_match_oracle(fuse, mf, smoother):
+    """Residual + restriction in one pass and the prolongation folded into the
+    first post-sweep (fuse 1) or separate kernels (fuse 0, the default), with
+    matrix-free or assembled fine levels, Jacobi or Chebyshev smoothing: a
+    three-level hierarchy against the oracle at forced PCG counts."""
+    w = W.beam(48, 12, 12, seed=5, volumes=True, alpha_edge=1e-8, alpha_vol=1e-9)
+    sim, body, pos, vel, ores, gres = run_both(w, 3, force_from_oracle=True, coarse_max=100,
+                                               fuse_transfers=fuse, matrix_free=mf,
+                                               smoother=smoother)
+    levels = [B.mgpbd_get_level(body.ctx, l)["n"] for l in range(B.mgpbd_num_levels(body.ctx))]
+    err = rel_pos_err(body.positions(), pos)
+    log("fuse %d mf %d smoother %d: levels %s, position error %.3e" % (fuse, mf, smoother, levels,
+                                                                     err))
+    assert len(levels) >= 3
+    assert err <= 1e-9
