@@ -49,6 +49,31 @@ __device__ __forceinline__ void block_range(int64_t items, int64_t &lo, int64_t 
   if (lo > items) lo = items;
 }
 
+// The items of this block's XCD (the union of block_range over the XCD's
+// blocks) visited in lockstep: the XCD's bpx blocks take consecutive chunks
+// of `chunk` items, block j the j-th chunk of every window of bpx chunks, so
+// the whole XCD sweeps one window at a time. Data shared by nearby items
+// (the vertex records of a row pass, the gathered entries of a vertex gather)
+// is then reused within a short time and stays in the XCD's L2, where
+// contiguous per-block ranges revisit it only after the XCD has streamed many
+// megabytes. Every item is visited exactly once: loop
+// for (c0 = first; c0 < hi; c0 += step) over items [c0, min(c0 + chunk, hi)).
+struct XcdStride {
+  int64_t hi, first, step;
+};
+__device__ __forceinline__ XcdStride xcd_stride(int64_t items, int64_t chunk) {
+  const int g = gridDim.x, b = blockIdx.x;
+  const int per = g / kNumXcd, rem = g % kNumXcd;
+  const int x = b % kNumXcd, j = b / kNumXcd;
+  const int bpx = per + (x < rem ? 1 : 0);
+  const int base = x * per + (x < rem ? x : rem);
+  const int64_t perb = (items + g - 1) / g;
+  int64_t lo = (int64_t)base * perb, hi = (int64_t)(base + bpx) * perb;
+  if (lo > items) lo = items;
+  if (hi > items) hi = items;
+  return {hi, lo + (int64_t)j * chunk, (int64_t)bpx * chunk};
+}
+
 // Deterministic grid-wide reductions in two kernels. The producing kernel
 // calls block_partials (fixed-tree sum per block, one partial per block); a
 // one-block finisher kernel calls sum_partials, which adds the partials in a

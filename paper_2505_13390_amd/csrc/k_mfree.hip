@@ -56,11 +56,10 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T>
   if (done && *done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
-  int64_t lo, hi;
-  block_range(A.nv, lo, hi);
-  for (int64_t base = lo; base < hi; base += R) {
+  const XcdStride S = xcd_stride(A.nv, R);
+  for (int64_t base = S.first; base < S.hi; base += S.step) {
     const int64_t v = base + grp;
-    const bool ok = v < hi;
+    const bool ok = v < S.hi;
     T sx = 0, sy = 0, sz = 0;
     if (ok) {
       const int64_t a = A.vptr[v], b = A.vptr[v + 1];
@@ -141,16 +140,16 @@ template <class T, class In, class Op>
 __global__ __launch_bounds__(kBlock, 8) void k_mf_rows(const int *done, MfView<T> A, In x, Op op,
                                                        double *partials) {
   if (done && *done) return;
-  int64_t lo, hi;
-  block_range(A.m, lo, hi);
+  const XcdStride S = xcd_stride(A.m, blockDim.x);
+  const int64_t hi = S.hi;
   double acc = 0.0;
   const int4 *rv4 = reinterpret_cast<const int4 *>(A.rv);
   // the vertex ids of the next row are loaded while this row is computed
-  int64_t c = lo + threadIdx.x;
+  int64_t c = S.first + threadIdx.x;
   int4 rn = c < hi ? rv4[c] : make_int4(0, 0, -1, -1);
-  for (; c < hi; c += blockDim.x) {
+  for (; c < hi; c += S.step) {
     const int4 r = rn;
-    const int64_t cn = c + blockDim.x;
+    const int64_t cn = c + S.step;
     if (cn < hi) rn = rv4[cn];
     const T s = mf_row(A, c, r) + A.alpha[c] * x(c);
     op(c, s, acc);
