@@ -19,8 +19,15 @@ _LIB = os.path.join(_HERE, "liboracle_mgpbd.so")
 OK, E_INVALID, E_NOMEM, E_NOT_CONVERGED, E_BREAKDOWN, E_SETUP = 0, 1, 2, 4, 5, 6
 
 
+# MGPBD_ORACLE_LIB names another build of the same source to load instead
+# (the sanitizer test builds one with -fsanitize=address,undefined)
+_OVERRIDE = os.environ.get("MGPBD_ORACLE_LIB")
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle (gcc, FP64, no contraction, no fast-math)."""
+    if _OVERRIDE:
+        return _OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
                                "-o", _LIB, _SRC, "-lm"])
