@@ -502,16 +502,6 @@ __global__ void k_d2f(int64_t n, const double *__restrict__ in, float *__restric
 void launch_d2f(int64_t n, const double *in, float *out, const int *done, hipStream_t s) {
   if (n) k_d2f<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
 }
-__global__ void k_f2d(int64_t n, const float *__restrict__ in, double *__restrict__ out,
-                      const int *done) {
-  if (done && *done) return;
-  int64_t lo, hi;
-  block_range(n, lo, hi);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) out[i] = (double)in[i];
-}
-void launch_f2d(int64_t n, const float *in, double *out, const int *done, hipStream_t s) {
-  if (n) k_f2d<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, in, out, done);
-}
 template <class T>
 __global__ void k_copy_t(int64_t n, const T *__restrict__ in, T *__restrict__ out, const int *done) {
   if (done && *done) return;

@@ -162,16 +162,23 @@ void launch_s_pcg_init(const SegTab &t, PcgCtl *ctl, const double *b, double *x,
 __global__ __launch_bounds__(kBlock) void k_s_pcg_init_p(SegTab t, const PcgCtl *ctl,
                                                          const double *__restrict__ r,
                                                          const double *__restrict__ z,
+                                                         const float *__restrict__ z32,
                                                          double *__restrict__ p,
-                                                         double *__restrict__ zold, int flexible,
+                                                         float *__restrict__ zold32,
                                                          double *partials) {
   SEG_BLOCK(t);
   double v[1] = {0.0};
   if (!ctl[seg].done) {
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      double zi = z[i];
+      double zi;
+      if (z32) {
+        const float zf = z32[i];
+        zi = (double)zf;
+        zold32[i] = zf;
+      } else {
+        zi = z[i];
+      }
       p[i] = zi;
-      if (flexible) zold[i] = zi;
       v[0] += r[i] * zi;
     }
   }
@@ -189,9 +196,9 @@ __global__ __launch_bounds__(kBlock) void k_s_fin_init_p(SegTab t, PcgCtl *ctl,
   }
 }
 void launch_s_pcg_init_p(const SegTab &t, PcgCtl *ctl, const double *r, const double *z,
-                         double *p, double *zold, bool flexible, double *partials,
+                         const float *z32, double *p, float *zold32, double *partials,
                          int *all_done, hipStream_t s) {
-  k_s_pcg_init_p<<<t.nblk, kBlock, 0, s>>>(t, ctl, r, z, p, zold, flexible ? 1 : 0, partials);
+  k_s_pcg_init_p<<<t.nblk, kBlock, 0, s>>>(t, ctl, r, z, z32, p, zold32, partials);
   k_s_fin_init_p<<<t.nseg, kBlock, 0, s>>>(t, ctl, partials);
   all_done_update(t, ctl, all_done, s);
 }
@@ -225,21 +232,39 @@ void launch_s_pcg_dot_pq(const SegTab &t, PcgCtl *ctl, const double *p, const do
   k_s_fin_pq<<<t.nseg, kBlock, 0, s>>>(t, ctl, partials);
 }
 
+// x += alpha p, r -= alpha q and the partial sums of |r|^2; with `first` the
+// new r also feeds the V-cycle's first fine-level step: its FP32 copy and the
+// first Jacobi iterate omega D^-1 r (k_d2f and k_jacobi_first's values). The
+// V-cycle runs over every row while any body is still iterating, so a
+// finished body's rows get the same values from its unchanged r.
 __global__ __launch_bounds__(kBlock) void k_s_pcg_update(SegTab t, const PcgCtl *ctl,
                                                          const double *__restrict__ p,
                                                          const double *__restrict__ q,
                                                          double *__restrict__ x,
                                                          double *__restrict__ r,
-                                                         double *partials) {
+                                                         double *partials, FirstSweep first) {
   SEG_BLOCK(t);
   double v[1] = {0.0};
-  if (!ctl[seg].done) {
+  const bool live = !ctl[seg].done;
+  const bool feed = (first.z64 || first.r32) && !*first.cycle_done;
+  if (live || feed) {
     const double alpha = ctl[seg].alpha;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      x[i] = x[i] + alpha * p[i];
-      double ri = r[i] - alpha * q[i];
-      r[i] = ri;
-      v[0] += ri * ri;
+      double ri;
+      if (live) {
+        x[i] = x[i] + alpha * p[i];
+        ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v[0] += ri * ri;
+      } else {
+        ri = r[i];
+      }
+      if (first.z64) first.z64[i] = ri * first.wd64[i];
+      if (first.r32) {
+        const float rf = (float)ri;
+        first.r32[i] = rf;
+        if (first.z32) first.z32[i] = rf * first.wd32[i];
+      }
     }
   }
   seg_partials<1>(v, partials);
@@ -264,34 +289,34 @@ __global__ __launch_bounds__(kBlock) void k_s_fin_update(SegTab t, PcgCtl *ctl,
   }
 }
 void launch_s_pcg_update(const SegTab &t, PcgCtl *ctl, const double *p, const double *q,
-                         double *x, double *r, double *partials, int *all_done, hipStream_t s) {
-  k_s_pcg_update<<<t.nblk, kBlock, 0, s>>>(t, ctl, p, q, x, r, partials);
+                         double *x, double *r, double *partials, int *all_done, hipStream_t s,
+                         const FirstSweep &first) {
+  k_s_pcg_update<<<t.nblk, kBlock, 0, s>>>(t, ctl, p, q, x, r, partials, first);
   k_s_fin_update<<<t.nseg, kBlock, 0, s>>>(t, ctl, partials);
   all_done_update(t, ctl, all_done, s);
 }
 
+// r^T z and, with the FP32 V-cycle, the flexible numerator r^T (z - zold)
+// (zold = the previous z, kept as the FP32 values it equals)
 __global__ __launch_bounds__(kBlock) void k_s_pcg_rz(SegTab t, const PcgCtl *ctl,
                                                      const double *__restrict__ r,
-                                                     double *__restrict__ z,
+                                                     const double *__restrict__ z,
                                                      const float *__restrict__ z32,
-                                                     double *__restrict__ zold, int flexible,
+                                                     float *__restrict__ zold32,
                                                      double *partials) {
   SEG_BLOCK(t);
   double v[2] = {0.0, 0.0};
   if (!ctl[seg].done) {
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      double zi;
+      const double ri = r[i];
       if (z32) {
-        zi = (double)z32[i];
-        z[i] = zi;
+        const float zf = z32[i];
+        const double zi = (double)zf;
+        v[0] += ri * zi;
+        v[1] += ri * (zi - (double)zold32[i]);
+        zold32[i] = zf;
       } else {
-        zi = z[i];
-      }
-      double ri = r[i];
-      v[0] += ri * zi;
-      if (flexible) {
-        v[1] += ri * (zi - zold[i]);
-        zold[i] = zi;
+        v[0] += ri * z[i];
       }
     }
   }
@@ -312,25 +337,29 @@ __global__ __launch_bounds__(kBlock) void k_s_fin_rz(SegTab t, PcgCtl *ctl,
     if (!(rho_new > 0.0)) c.done = 2;
   }
 }
-void launch_s_pcg_rz(const SegTab &t, PcgCtl *ctl, const double *r, double *z, const float *z32,
-                     double *zold, bool flexible, double *partials, int *all_done,
-                     hipStream_t s) {
-  k_s_pcg_rz<<<t.nblk, kBlock, 0, s>>>(t, ctl, r, z, z32, zold, flexible ? 1 : 0, partials);
-  k_s_fin_rz<<<t.nseg, kBlock, 0, s>>>(t, ctl, partials, flexible ? 1 : 0);
-  (void)all_done;
+void launch_s_pcg_rz(const SegTab &t, PcgCtl *ctl, const double *r, const double *z,
+                     const float *z32, float *zold32, double *partials, hipStream_t s) {
+  k_s_pcg_rz<<<t.nblk, kBlock, 0, s>>>(t, ctl, r, z, z32, zold32, partials);
+  k_s_fin_rz<<<t.nseg, kBlock, 0, s>>>(t, ctl, partials, z32 ? 1 : 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_s_pcg_pupdate(SegTab t, const PcgCtl *ctl,
                                                           const double *__restrict__ z,
+                                                          const float *__restrict__ z32,
                                                           double *__restrict__ p) {
   SEG_BLOCK(t);
   if (ctl[seg].done) return;
   const double beta = ctl[seg].beta;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) p[i] = z[i] + beta * p[i];
+  if (z32) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+      p[i] = (double)z32[i] + beta * p[i];
+  } else {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) p[i] = z[i] + beta * p[i];
+  }
 }
-void launch_s_pcg_pupdate(const SegTab &t, const PcgCtl *ctl, const double *z, double *p,
-                          hipStream_t s) {
-  k_s_pcg_pupdate<<<t.nblk, kBlock, 0, s>>>(t, ctl, z, p);
+void launch_s_pcg_pupdate(const SegTab &t, const PcgCtl *ctl, const double *z, const float *z32,
+                          double *p, hipStream_t s) {
+  k_s_pcg_pupdate<<<t.nblk, kBlock, 0, s>>>(t, ctl, z, z32, p);
 }
 
 // ------------------------------------------------------------ reductions

@@ -126,7 +126,6 @@ template <class T> void launch_prolong(int64_t n, const int32_t *agg, const T *p
 
 
 void launch_d2f(int64_t n, const double *in, float *out, const int *done, hipStream_t s);
-void launch_f2d(int64_t n, const float *in, double *out, const int *done, hipStream_t s);
 template <class T> void launch_copy_t(int64_t n, const T *in, T *out, const int *done, hipStream_t s);
 template <class T> void launch_zero_t(int64_t n, T *out, const int *done, hipStream_t s);
 void launch_copy(int64_t n, const double *in, double *out, const int *done, hipStream_t s);

@@ -38,18 +38,32 @@ struct SegTable {
 // when every body's solve has ended) ----
 void launch_s_pcg_init(const SegTab &t, PcgCtl *ctl, const double *b, double *x, double *r,
                        double *partials, int *all_done, hipStream_t s);
+// The preconditioned residual z comes either as FP64 (z, FP64 V-cycle:
+// Fletcher-Reeves beta) or as the FP32 V-cycle's output z32 (z = (double) z32
+// exactly: flexible beta, with zold32 = the previous z32; z is then not used)
 void launch_s_pcg_init_p(const SegTab &t, PcgCtl *ctl, const double *r, const double *z,
-                         double *p, double *zold, bool flexible, double *partials,
+                         const float *z32, double *p, float *zold32, double *partials,
                          int *all_done, hipStream_t s);
 void launch_s_pcg_dot_pq(const SegTab &t, PcgCtl *ctl, const double *p, const double *q,
                          double *partials, hipStream_t s);
+// What the V-cycle's first fine-level step needs from the new residual,
+// written by the PCG update (all null: nothing): z64 = r wd64 (FP64 cycle), or
+// r32 = (float) r and z32 = r32 wd32 (FP32 cycle); cycle_done is the flag that
+// skips the V-cycle (required when anything is written)
+struct FirstSweep {
+  const int *cycle_done = nullptr;
+  const double *wd64 = nullptr;
+  double *z64 = nullptr;
+  const float *wd32 = nullptr;
+  float *r32 = nullptr, *z32 = nullptr;
+};
 void launch_s_pcg_update(const SegTab &t, PcgCtl *ctl, const double *p, const double *q,
-                         double *x, double *r, double *partials, int *all_done, hipStream_t s);
-void launch_s_pcg_rz(const SegTab &t, PcgCtl *ctl, const double *r, double *z, const float *z32,
-                     double *zold, bool flexible, double *partials, int *all_done,
-                     hipStream_t s);
-void launch_s_pcg_pupdate(const SegTab &t, const PcgCtl *ctl, const double *z, double *p,
-                          hipStream_t s);
+                         double *x, double *r, double *partials, int *all_done, hipStream_t s,
+                         const FirstSweep &first = FirstSweep());
+void launch_s_pcg_rz(const SegTab &t, PcgCtl *ctl, const double *r, const double *z,
+                     const float *z32, float *zold32, double *partials, hipStream_t s);
+void launch_s_pcg_pupdate(const SegTab &t, const PcgCtl *ctl, const double *z, const float *z32,
+                          double *p, hipStream_t s);
 
 // ---- per-body reductions into out[seg] ----
 void launch_s_dot(const SegTab &t, const double *a, const double *b, double *out,

@@ -1057,7 +1057,7 @@ void Solver::refresh() {
 void Solver::ensure_vectors() {
   const int64_t n = lev[0]->n;
   x.reserve(n); r.reserve(n); z.reserve(n); p.reserve(n); q.reserve(n);
-  if (mixed()) zold.reserve(n);
+  if (mixed()) zold32.reserve(n);
   ctl.reserve(nb);
   ensure_pinned(std::max<size_t>(4096, sizeof(PcgCtl) * (size_t)nb + 64));
 }
@@ -1239,6 +1239,8 @@ void Solver::vcycle(int l, const T *r, T *z) {
   } else if (fuse && pre >= 2) {
     launch_jacobi_scaled<T>(A, wd, r, cur, done, st);
     k0 = 2;
+  } else if (l == 0 && first_ready) {
+    first_ready = false;   // the PCG update wrote omega D^-1 r into cur
   } else {
     launch_jacobi_first<T>(L.n, wd, r, cur, done, st);
   }
@@ -1313,6 +1315,31 @@ void Solver::vcycle(int l, const T *r, T *z) {
 }
 
 // ------------------------------------------------------------ PCG
+// Where the PCG update can write the V-cycle's first fine-level step: the
+// FP32 residual of the mixed cycle always, and the first Jacobi iterate
+// omega D^-1 r when vcycle(0) would form it elementwise (Jacobi smoother,
+// matrix-free fine level, at least one pre-sweep), into the buffer vcycle's
+// ping-pong picks for it (the last write of the level lands in z).
+FirstSweep Solver::first_sweep_targets() {
+  FirstSweep f;
+  Level &F = *lev[0];
+  const bool flex = mixed();
+  f.cycle_done = done_ptr();
+  if (flex) f.r32 = F.r32.p;
+  const bool mf0 = flex ? mf32.ok() : mf.ok();
+  if (!(F.smooth_here && opt.smoother == 0 && opt.pre_sweeps >= 1 && mf0)) return f;
+  const int writes = opt.pre_sweeps + opt.post_sweeps;
+  const bool into_z = (writes % 2) != 0;
+  if (flex) {
+    f.wd32 = F.wdinv32.p;
+    f.z32 = into_z ? F.z32.p : F.t32.p;
+  } else {
+    f.wd64 = F.wdinv.p;
+    f.z64 = into_z ? z.p : F.t.p;
+  }
+  return f;
+}
+
 void Solver::iterate_once(int k) {
   Level &F = *lev[0];
   const int64_t n = F.n;
@@ -1348,18 +1375,21 @@ void Solver::iterate_once(int k) {
     mark(2);
   }
   if (nb > 1) launch_s_pcg_dot_pq(t, ctl.p, p.p, q.p, partials(), st);
-  launch_s_pcg_update(t, ctl.p, p.p, q.p, x.p, r.p, partials(), all_done.p, st);
+  const FirstSweep fs = first_sweep_targets();
+  launch_s_pcg_update(t, ctl.p, p.p, q.p, x.p, r.p, partials(), all_done.p, st, fs);
+  first_ready = fs.z32 != nullptr || fs.z64 != nullptr;
   prof_k = opt.profile_spmv ? k : -1;
   if (flex) {
-    launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
+    if (!fs.r32) launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
     vcycle<float>(0, F.r32.p, F.z32.p);
-    launch_s_pcg_rz(t, ctl.p, r.p, z.p, F.z32.p, zold.p, true, partials(), all_done.p, st);
+    launch_s_pcg_rz(t, ctl.p, r.p, nullptr, F.z32.p, zold32.p, partials(), st);
   } else {
     vcycle<double>(0, r.p, z.p);
-    launch_s_pcg_rz(t, ctl.p, r.p, z.p, nullptr, zold.p, false, partials(), all_done.p, st);
+    launch_s_pcg_rz(t, ctl.p, r.p, z.p, nullptr, nullptr, partials(), st);
   }
   prof_k = -1;
-  launch_s_pcg_pupdate(t, ctl.p, z.p, p.p, st);
+  first_ready = false;
+  launch_s_pcg_pupdate(t, ctl.p, z.p, flex ? F.z32.p : nullptr, p.p, st);
 }
 
 void Solver::apply_fine(const double *x, double *y) {
@@ -1410,11 +1440,12 @@ std::vector<PcgResult> Solver::pcg(const double *b, double *x_out, double tol, i
   if (mixed()) {
     launch_d2f(n, r.p, F.r32.p, done_ptr(), st);
     vcycle<float>(0, F.r32.p, F.z32.p);
-    launch_f2d(n, F.z32.p, z.p, done_ptr(), st);
+    launch_s_pcg_init_p(t, ctl.p, r.p, nullptr, F.z32.p, p.p, zold32.p, partials(), all_done.p,
+                        st);
   } else {
     vcycle<double>(0, r.p, z.p);
+    launch_s_pcg_init_p(t, ctl.p, r.p, z.p, nullptr, p.p, nullptr, partials(), all_done.p, st);
   }
-  launch_s_pcg_init_p(t, ctl.p, r.p, z.p, p.p, zold.p, mixed(), partials(), all_done.p, st);
   const int chunk = std::max(1, opt.check_every);
   // events around the fine-level product are recorded on the stream, so the
   // profiled solve launches kernels directly instead of replaying the graph

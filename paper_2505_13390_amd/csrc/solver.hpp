@@ -187,7 +187,8 @@ class Solver {
   DevBuf<PcgCtl> ctl;
   DevBuf<int> all_done;
   DevBuf<double> red_partials;
-  DevBuf<double> x, r, z, p, q, zold;
+  DevBuf<double> x, r, z, p, q;
+  DevBuf<float> zold32;   // FP32 V-cycle: the previous z (flexible beta)
   DevBuf<double> dscal;
   DevBuf<int> flags;
   DevBuf<unsigned long long> amax;
@@ -208,6 +209,10 @@ class Solver {
   // descent, return, exit); prof_k = slot of the V-cycle being recorded
   std::vector<hipEvent_t> lev_ev;
   int prof_k = -1;
+  // the PCG update already wrote the fine level's first Jacobi iterate (and
+  // the FP32 residual): the next vcycle(0) skips that step
+  bool first_ready = false;
+  FirstSweep first_sweep_targets();
   void pmark(int l, int j);
 
   double *partials() { return red_partials.p; }
