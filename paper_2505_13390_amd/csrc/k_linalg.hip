@@ -401,7 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t na, const int64_t *
                                                      const int32_t *__restrict__ mem,
                                                      const T *__restrict__ p,
                                                      const T *__restrict__ res,
-                                                     T *__restrict__ rc, const int *done) {
+                                                     T *__restrict__ rc, const int *done,
+                                                     CoarseFirst<T> first) {
   if (done && *done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
@@ -417,7 +418,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t na, const int64_t *
       s += p[i] * res[i];
     }
     s = group_sum<G>(s);
-    if (ok && sub == 0) rc[a] = s;
+    if (ok && sub == 0) {
+      rc[a] = s;
+      if (first.z) first.z[a] = s * first.wd[a];
+    }
   }
 }
 
@@ -428,7 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_sum(int64_t na,
                                                          const int64_t *__restrict__ ap,
                                                          const int32_t *__restrict__ mem,
                                                          const T *__restrict__ w,
-                                                         T *__restrict__ rc, const int *done) {
+                                                         T *__restrict__ rc, const int *done,
+                                                         CoarseFirst<T> first) {
   if (done && *done) return;
   constexpr int R = kBlock / G;
   const int sub = threadIdx.x % G, grp = threadIdx.x / G;
@@ -441,32 +446,51 @@ __global__ __launch_bounds__(kBlock) void k_restrict_sum(int64_t na,
     T s = 0;
     for (int64_t k = b0 + sub; k < b1; k += G) s += w[mem[k]];
     s = group_sum<G>(s);
-    if (ok && sub == 0) rc[a] = s;
+    if (ok && sub == 0) {
+      rc[a] = s;
+      if (first.z) first.z[a] = s * first.wd[a];
+    }
   }
 }
 template <class T>
 void launch_restrict_sum(int64_t na, const int64_t *ap, const int32_t *mem, const T *w, T *rc,
-                         int lanes, const int *done, hipStream_t s) {
+                         int lanes, const int *done, hipStream_t s, CoarseFirst<T> first) {
   if (na == 0) return;
   const int grid = grid_for(na * lanes, kBlock);
   switch (lanes) {
-    case 64: k_restrict_sum<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
-    case 32: k_restrict_sum<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
-    case 16: k_restrict_sum<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
-    default: k_restrict_sum<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done); break;
+    case 64:
+      k_restrict_sum<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done, first);
+      break;
+    case 32:
+      k_restrict_sum<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done, first);
+      break;
+    case 16:
+      k_restrict_sum<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done, first);
+      break;
+    default:
+      k_restrict_sum<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, w, rc, done, first);
+      break;
   }
 }
 
 template <class T>
 void launch_restrict(int64_t na, const int64_t *ap, const int32_t *mem, const T *p, const T *res,
-                     T *rc, int lanes, const int *done, hipStream_t s) {
+                     T *rc, int lanes, const int *done, hipStream_t s, CoarseFirst<T> first) {
   if (na == 0) return;
   const int grid = grid_for(na * lanes, kBlock);
   switch (lanes) {
-    case 64: k_restrict<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
-    case 32: k_restrict<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
-    case 16: k_restrict<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
-    default: k_restrict<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done); break;
+    case 64:
+      k_restrict<64, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done, first);
+      break;
+    case 32:
+      k_restrict<32, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done, first);
+      break;
+    case 16:
+      k_restrict<16, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done, first);
+      break;
+    default:
+      k_restrict<8, T><<<grid, kBlock, 0, s>>>(na, ap, mem, p, res, rc, done, first);
+      break;
   }
 }
 
@@ -684,9 +708,9 @@ void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, DevBu
   template void launch_cheb<T>(const CsrView<T> &, const T *, const T *, const T *, const int32_t *, \
                                int, int, const T *, T *, T *, const int *, hipStream_t);            \
   template void launch_restrict<T>(int64_t, const int64_t *, const int32_t *, const T *, const T *, \
-                                   T *, int, const int *, hipStream_t);                             \
+                                   T *, int, const int *, hipStream_t, CoarseFirst<T>);             \
   template void launch_restrict_sum<T>(int64_t, const int64_t *, const int32_t *, const T *, T *,  \
-                                       int, const int *, hipStream_t);                             \
+                                       int, const int *, hipStream_t, CoarseFirst<T>);             \
   template void launch_jacobi_prolong<T>(const CsrView<T> &, const T *, const T *, const T *,     \
                                          const T *, const int32_t *, const T *, T *, const int *, \
                                          hipStream_t);                                            \

@@ -85,12 +85,19 @@ template <class T> void launch_cheb_prolong(const CsrView<T> &A, const T *r, con
                                             int k, const T *zi, const T *p, const int32_t *agg,
                                             const T *e, T *d, T *zo, const int *done,
                                             hipStream_t s);
+// With z set, a restriction also writes z[a] = rc[a] wd[a], the coarse level's
+// first Jacobi sweep from zero (the values k_jacobi_first would write there).
+template <class T>
+struct CoarseFirst {
+  const T *wd = nullptr;
+  T *z = nullptr;
+};
 // rc[a] = sum of w_i over the members i of aggregate a (ascending, RL lanes
 // with the fixed tree of the restriction): the restriction when the residual
 // pass already stored w = p (r - A z)
 template <class T> void launch_restrict_sum(int64_t na, const int64_t *ap, const int32_t *mem,
                                             const T *w, T *rc, int lanes, const int *done,
-                                            hipStream_t s);
+                                            hipStream_t s, CoarseFirst<T> first = {});
 // rc = P^T (r - A z) in one pass over the aggregates [0, na): G lanes per
 // aggregate form each member row's residual (ascending members) and add
 // p_i res_i in that order; the fine residual is not stored
@@ -119,7 +126,8 @@ template <class T> void launch_cheb(const CsrView<T> &A, const T *r, const T *di
 // aggregate, each summing a strided share, then a fixed-tree lane sum
 template <class T> void launch_restrict(int64_t n_agg, const int64_t *agg_ptr,
                                         const int32_t *agg_mem, const T *p, const T *res, T *rc,
-                                        int lanes, const int *done, hipStream_t s);
+                                        int lanes, const int *done, hipStream_t s,
+                                        CoarseFirst<T> first = {});
 // z_i += p_i ec[agg_i]
 template <class T> void launch_prolong(int64_t n, const int32_t *agg, const T *p, const T *ec,
                                        T *z, const int *done, hipStream_t s);

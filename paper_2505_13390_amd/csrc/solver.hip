@@ -1150,7 +1150,7 @@ void Solver::gs_vcycle(int l, const T *r, T *z) {
 // transfers between level l and l + 1: P^T (restriction) and P (prolongation
 // added to z); one value per row, or the Q blocks when K > 1
 template <class T>
-void Solver::restrict_to(int l, const T *res, T *rc) {
+void Solver::restrict_to(int l, const T *res, T *rc, CoarseFirst<T> first) {
   Level &L = *lev[l];
   Level &C = *lev[l + 1];
   if (L.K > 1)
@@ -1158,7 +1158,21 @@ void Solver::restrict_to(int l, const T *res, T *rc) {
                          res, rc, done_ptr(), st);
   else
     launch_restrict<T>(C.n, L.agg_ptr.p, L.agg_mem.p, Buf<T>::p(L), res, rc, L.rlanes,
-                       done_ptr(), st);
+                       done_ptr(), st, first);
+}
+
+// The restriction into level l (one candidate) also writes that level's first
+// Jacobi sweep from zero, omega D^-1 r, when vcycle(l) would start with it:
+// Jacobi smoother, at least one pre-sweep, a level that smooths, outside the
+// fused tail and the fused residual-restriction pass. On an assembled level
+// this replaces the pass that forms the first two sweeps together (whose
+// gather reads r and omega D^-1 for every entry): the second sweep then
+// gathers the stored iterate like every later one. Same values either way.
+bool Solver::first_from_restriction(int l) const {
+  if (l < 1 || l >= nlev) return false;
+  if (tail_l0 > 0 && l >= tail_l0) return false;
+  return lev[l]->smooth_here && lev[l - 1]->K == 1 && opt.smoother == 0 &&
+         opt.pre_sweeps >= 1 && !opt.fuse_transfers;
 }
 template <class T>
 void Solver::prolong_from(int l, const T *ec, T *z) {
@@ -1201,7 +1215,8 @@ void Solver::vcycle(int l, const T *r, T *z) {
   // z1 = omega D^-1 r on the fly. A matrix-free level keeps the elementwise
   // first sweep: its gather would fetch two vectors per incidence instead of
   // one, which costs more than the separate kernel.
-  const bool fuse = (M == nullptr) && opt.smoother == 0;
+  const bool from_restriction = first_from_restriction(l);
+  const bool fuse = (M == nullptr) && opt.smoother == 0 && !from_restriction;
   const bool cheb = opt.smoother == 1;
   const int steps = std::max(1, std::max(pre, post));
   // The iterate ping-pongs between z and the level's scratch vector; the
@@ -1236,6 +1251,8 @@ void Solver::vcycle(int l, const T *r, T *z) {
   } else if (cheb) {
     launch_cheb_first<T>(L.n, r, Buf<T>::dinv(L), Buf<T>::cheb(L), L.rowseg.p, steps,
                          Buf<T>::dir(L), cur, done, st);
+  } else if (from_restriction) {
+    // the restriction into this level wrote omega D^-1 r into cur
   } else if (fuse && pre >= 2) {
     launch_jacobi_scaled<T>(A, wd, r, cur, done, st);
     k0 = 2;
@@ -1261,6 +1278,13 @@ void Solver::vcycle(int l, const T *r, T *z) {
     T *rc = Buf<T>::r(C).p, *ec = Buf<T>::z(C).p;
     const T *pl = Buf<T>::p(L);
     T *res = Buf<T>::res(L).p;
+    // the coarse level's first iterate goes where its vcycle() starts writing
+    // (the buffer whose parity leaves the last write in ec)
+    CoarseFirst<T> cf;
+    if (first_from_restriction(l + 1)) {
+      cf.wd = Buf<T>::wdinv(C);
+      cf.z = ((pre + post) % 2) ? ec : Buf<T>::t(C).p;
+    }
     if (!M && opt.fuse_transfers && L.K == 1) {
       launch_residual_restrict<T>(A, r, cur, C.n, L.agg_ptr.p, L.agg_mem.p, pl, rc, done, st);
     } else if (M && L.K == 1) {
@@ -1268,11 +1292,11 @@ void Solver::vcycle(int l, const T *r, T *z) {
       // row order (coalesced), so the restriction gathers one scattered value
       // per member instead of two; the terms and their order are unchanged
       launch_mf_residual_scaled<T>(*M, r, cur, pl, res, done, st);
-      launch_restrict_sum<T>(C.n, L.agg_ptr.p, L.agg_mem.p, res, rc, L.rlanes, done, st);
+      launch_restrict_sum<T>(C.n, L.agg_ptr.p, L.agg_mem.p, res, rc, L.rlanes, done, st, cf);
     } else {
       if (M) launch_mf_residual<T>(*M, r, cur, res, done, st);
       else launch_residual<T>(A, r, cur, res, done, st);
-      restrict_to<T>(l, res, rc);
+      restrict_to<T>(l, res, rc, cf);
     }
     pmark(l, 1);
     vcycle<T>(l + 1, rc, ec);

@@ -213,6 +213,8 @@ class Solver {
   // the FP32 residual): the next vcycle(0) skips that step
   bool first_ready = false;
   FirstSweep first_sweep_targets();
+  // level l >= 1 takes its first Jacobi iterate from the restriction into it
+  bool first_from_restriction(int l) const;
   void pmark(int l, int j);
 
   double *partials() { return red_partials.p; }
@@ -240,7 +242,7 @@ class Solver {
   void galerkin_numeric(int l);
   int64_t qr_level(int l);
   void galerkin_symbolic_k(int l);
-  template <class T> void restrict_to(int l, const T *res, T *rc);
+  template <class T> void restrict_to(int l, const T *res, T *rc, CoarseFirst<T> first = {});
   template <class T> void prolong_from(int l, const T *ec, T *z);
   void power_omega(int l);
   void tune_lanes(int l);
