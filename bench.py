@@ -169,7 +169,8 @@ def bench_batch(args, B, W):
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     opt = B.mgpbd_default_options(precision=prec, reuse_interval=args.reuse,
                                   matrix_free={"mf": 1, "csr": 0, "auto": 2}[args.fine],
-                                  lmax_scale=args.lmax_scale or 1.05,
+                                  lmax_scale=args.lmax_scale or (1.5 if args.config == "C4"
+                                                                 else 1.05),
                                   smoother={"jacobi": 0, "chebyshev": 1, "gs": 2}[args.smoother])
     if args.max_pcg:
         opt.max_pcg = args.max_pcg
@@ -244,6 +245,7 @@ def bench_batch(args, B, W):
         "dtype": "f64" if prec == B.PREC_FP64 else "f32 V-cycle / f64 PCG", "data": "synthetic",
         "config": {"workload": ("batch_64_beams_n4-24" if args.config == "C3"
                                 else "stiff_ellipsoid_x%d" % len(ws)),
+                   "lmax_scale": opt.lmax_scale,
                    "bodies": len(ws), "rows": sum(rows),
                    "mode": ("sequential contexts" if args.sequential else
                             "%d batch(es) of %s bodies" % (len(groups),
@@ -280,7 +282,8 @@ def main():
                          "64-beam batch; C4: the stiff ellipsoid copies; A0/A1: the ARAP beams")
     ap.add_argument("--lmax-scale", type=float, default=None,
                     help="margin on the power-method lambda_max (default 1.05; 1.5 for the "
-                         "ARAP beams, whose matrix drifts further between lazy setups)")
+                         "ARAP beams and the stiff copies, whose matrices drift further between "
+                         "lazy setups)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: mixed for C2, C3 and C4, fp64 otherwise")
     ap.add_argument("--sequential", action="store_true",
