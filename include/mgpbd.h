@@ -127,6 +127,13 @@ typedef struct {
                            kernels (the default: the fused passes' extra dependent loads
                            cost more than the launches they save on the workloads
                            measured): 0 */
+  int32_t resetup_on_breakdown; /* 1: when PCG breaks down (p^T A p <= 0 or r^T z <= 0)
+                           under a hierarchy kept from an earlier global iteration (the
+                           lazy setup of Sec. 4.2, with the smoother weights of Sec. 4.5),
+                           set up afresh for the current A and solve that iteration
+                           again, once; setup_ran reports 2 for it. In a batch the whole
+                           system is set up again and every body solved again. 0: return
+                           MGPBD_E_BREAKDOWN: 1 */
 } mgpbd_options;
 
 /* Tetrahedral body. All arrays host, read during mgpbd_create only.
@@ -175,7 +182,8 @@ typedef struct {
   double *bnorm;        /* |b| at each global iteration */
   int32_t *pcg_iters;   /* PCG iterations of each solve */
   double *pcg_ratio;    /* final recurrence |r| / |b| of each solve */
-  int32_t *setup_ran;   /* 1 where the AMG setup ran at that iteration */
+  int32_t *setup_ran;   /* 1 where the AMG setup ran at that iteration, 2 where it ran
+                           again after a breakdown (resetup_on_breakdown) */
   int32_t iters_done;   /* global iterations executed */
   double ms_setup;      /* time spent in the setup and in the Galerkin refreshes (hipEvents) */
   double ms_pcg;        /* time spent in the PCG loops (hipEvents) */

@@ -97,6 +97,9 @@ typedef struct orc_opts {
   int n_cand;          /* near-kernel candidates per level K (Sec. 4.3 uses six): 1 */
   int power_max;       /* power-method step cap: 500 */
   double power_tol;    /* power-method stop: eigen-residual <= power_tol * estimate: 1e-2 */
+  int resetup_on_breakdown; /* 1: a PCG breakdown under a hierarchy kept from an earlier
+                               iteration sets up afresh for the current A and solves
+                               again (once): 1 */
 } orc_opts;
 
 void orc_default_opts(orc_opts *o) {
@@ -122,6 +125,7 @@ void orc_default_opts(orc_opts *o) {
   o->n_cand = 1;
   o->power_max = 500;
   o->power_tol = 1e-2;
+  o->resetup_on_breakdown = 1;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1625,6 +1629,20 @@ int orc_sim_step(orc_sim *s, double *pos, double *vel, int n_iters, double *bnor
     double ratio = 0.0;
     int ps = orc_pcg((hier_t *)s->hier, b, s->o.tol, s->o.max_pcg, 1,
                      force_pcg ? force_pcg[ite] : 0, dl, &its, &ratio);
+    if (ps == ORC_E_BREAKDOWN && !due && s->o.resetup_on_breakdown) {
+      /* the lazy setup (Sec. 4.2) keeps the hierarchy and the smoother weights
+         of Sec. 4.5 while they still precondition A; once they do not (the
+         V-cycle is no longer positive definite for this A), set up afresh for
+         the current A and solve this iteration again */
+      if (setup_out) setup_out[ite] = 2;
+      orc_hier_free((hier_t *)s->hier);
+      s->hier = orc_hier_build(m, s->A.rowptr, s->A.col, s->A.val, &s->o, &st);
+      if (!s->hier) break;
+      its = 0;
+      ratio = 0.0;
+      ps = orc_pcg((hier_t *)s->hier, b, s->o.tol, s->o.max_pcg, 1,
+                   force_pcg ? force_pcg[ite] : 0, dl, &its, &ratio);
+    }
     if (pcg_iters_out) pcg_iters_out[ite] = its;
     if (ratio_out) ratio_out[ite] = ratio;
     if (ps == ORC_E_BREAKDOWN) { st = ps; break; }

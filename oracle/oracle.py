@@ -42,7 +42,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("reuse_interval", C.c_int), ("b_mode", C.c_int),
                 ("eps_b", C.c_double), ("flexible", C.c_int), ("lmax_scale", C.c_double),
                 ("smoother", C.c_int), ("n_cand", C.c_int), ("power_max", C.c_int),
-                ("power_tol", C.c_double)]
+                ("power_tol", C.c_double), ("resetup_on_breakdown", C.c_int)]
 
 
 _lib = None

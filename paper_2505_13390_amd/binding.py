@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("spmv_tile", C.c_int32), ("spmv_lanes", C.c_int32),
                 ("matrix_free", C.c_int32), ("smoother", C.c_int32), ("n_cand", C.c_int32),
                 ("power_max", C.c_int32), ("power_tol", C.c_double),
-                ("vcycle_tail", C.c_int32), ("fuse_transfers", C.c_int32)]
+                ("vcycle_tail", C.c_int32), ("fuse_transfers", C.c_int32),
+                ("resetup_on_breakdown", C.c_int32)]
 
 
 class Mesh(C.Structure):

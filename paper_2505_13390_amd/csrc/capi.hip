@@ -170,6 +170,8 @@ void check_options(const mgpbd_options &o) {
   MG_REQUIRE(o.vcycle_tail >= 0, MGPBD_E_INVALID_ARG, "vcycle_tail");
   MG_REQUIRE(o.fuse_transfers == 0 || o.fuse_transfers == 1, MGPBD_E_INVALID_ARG,
              "fuse_transfers must be 0 or 1");
+  MG_REQUIRE(o.resetup_on_breakdown == 0 || o.resetup_on_breakdown == 1, MGPBD_E_INVALID_ARG,
+             "resetup_on_breakdown must be 0 or 1");
   MG_REQUIRE(o.tol >= 0.0 && o.lmax_scale > 0.0, MGPBD_E_INVALID_ARG, "tol / lmax_scale");
   MG_REQUIRE(o.precision == MGPBD_PREC_FP64 || o.precision == MGPBD_PREC_MIXED,
              MGPBD_E_INVALID_ARG, "precision");
@@ -401,6 +403,21 @@ void run_frame(mgpbd_ctx *c, double *const xyz[3], double *const vxyz[3], int n_
     part.start(st);
     std::vector<PcgResult> pr = S.pcg(c->b.p, S.dl(), c->opt.tol, c->opt.max_pcg, fv.data());
     ms_pcg += part.stop(st);
+    bool broke = false;
+    for (int k = 0; k < nb; ++k) broke = broke || (!stopped[k] && pr[k].status == 2);
+    if (broke && !due && c->opt.resetup_on_breakdown) {
+      // the lazy setup keeps the hierarchy and its smoother weights while they
+      // still precondition A; this A they no longer do (the V-cycle is not
+      // positive definite for it): set up afresh and solve the iteration again
+      for (int k = 0; k < nb; ++k)
+        if (!stopped[k] && stats && stats[k].setup_ran) stats[k].setup_ran[ite] = 2;
+      part.start(st);
+      S.setup();
+      ms_setup += part.stop(st);
+      part.start(st);
+      pr = S.pcg(c->b.p, S.dl(), c->opt.tol, c->opt.max_pcg, fv.data());
+      ms_pcg += part.stop(st);
+    }
     for (int k = 0; k < nb; ++k) {
       if (stopped[k]) continue;
       if (stats && stats[k].pcg_iters) stats[k].pcg_iters[ite] = pr[k].iters;
@@ -479,6 +496,7 @@ void mgpbd_default_options(mgpbd_options *o) {
   o->power_tol = 1e-2;
   o->vcycle_tail = 0;
   o->fuse_transfers = 0;
+  o->resetup_on_breakdown = 1;
 }
 
 mgpbd_status mgpbd_solver_create(const mgpbd_options *opt, mgpbd_ctx **out) {

@@ -11,7 +11,7 @@ from paper_2505_13390_amd import workloads as W
 COMMON = ("theta", "gs_sweeps", "pre_sweeps", "post_sweeps", "lambda_min", "coarse_max",
           "dense_max", "max_levels", "power_iters", "omega_relax", "tol", "max_pcg", "seed",
           "reuse_interval", "b_mode", "eps_b", "lmax_scale", "smoother", "n_cand", "power_max",
-          "power_tol")
+          "power_tol", "resetup_on_breakdown")
 
 
 def log(*a):

@@ -50,7 +50,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.smoother == 0
     assert o.n_cand == 1
     assert o.power_max == 500 and o.power_tol == 1e-2
-    assert o.vcycle_tail == 0 and o.fuse_transfers == 0
+    assert o.vcycle_tail == 0 and o.fuse_transfers == 0 and o.resetup_on_breakdown == 1
 
 
 def test_null_arguments_rejected_without_device_work():

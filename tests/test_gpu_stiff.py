@@ -6,7 +6,9 @@ tests/golden/make_c4_bnorm.py with the same 20 forced PCG iterations per solve
 and the same lmax_scale 1.5: as one body, and as body 0 of a batch of two
 copies. Both sides start each solve from the same A and b only at iteration 0;
 later iterations see positions that differ by the rounding of the previous
-solves, so the history is compared to a bar derived from that (below)."""
+solves, so the history is compared to a bar derived from that (below). At
+the default margin 1.05 the same frame breaks down at iteration 5 under the
+hierarchy kept from iteration 0 and sets up afresh there, on both sides."""
 import os
 
 import numpy as np
@@ -33,10 +35,15 @@ LMAX_SCALE = 1.5
 FP64_BNORM = 1e-7
 
 
-def golden():
-    path = os.path.join(GOLDEN, "c4_copy0_frame0_bnorm.txt")
+def golden(name="c4_copy0_frame0_bnorm.txt"):
+    path = os.path.join(GOLDEN, name)
     rows = [l.split() for l in open(path) if not l.startswith("#")]
     return np.array([float(r[1]) for r in rows]), np.array([float(r[2]) for r in rows])
+
+
+def golden_setup(name):
+    path = os.path.join(GOLDEN, name)
+    return [int(l.split()[3]) for l in open(path) if not l.startswith("#")]
 
 
 def _check(tag, bn, ref):
@@ -77,3 +84,28 @@ def test_c4_first_frame_bnorm_history_in_a_batch():
     res = batch.step(N_ITERS)
     _check("C4 batch body 0", res[0]["bnorm"], ref)
     batch.close()
+
+
+def test_c4_default_margin_sets_up_afresh_after_breakdown():
+    """The same frame at the default margin 1.05: the hierarchy and omega
+    kept from iteration 0 stop preconditioning A at iteration 5 and PCG breaks
+    down; with resetup_on_breakdown (the default) both sides set up afresh at
+    that iteration and go on. The setup flags must match the oracle's
+    (tests/golden/c4_copy0_frame0_bnorm_lmax105.txt) and |b| of every
+    iteration must stay within the bar above."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    name = "c4_copy0_frame0_bnorm_lmax105.txt"
+    ref, _ = golden(name)
+    ref_setup = golden_setup(name)
+    assert 2 in ref_setup
+    w = W.stiff_c4(copies=1)[0]
+    _, go = opts()
+    body = B.Body(w, go)
+    B.mgpbd_force_pcg_iters(body.ctx, [FORCED] * N_ITERS)
+    r = body.step(N_ITERS)
+    log("C4 default margin: setup oracle %s gpu %s" % (ref_setup, r["setup_ran"].tolist()))
+    assert r["setup_ran"].tolist() == ref_setup
+    assert (r["pcg_iters"] == FORCED).all()
+    _check("C4 body, default margin", r["bnorm"], ref)
+    body.close()

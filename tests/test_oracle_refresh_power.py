@@ -208,3 +208,39 @@ def test_power_method_stopping_test_on_the_larger_ellipsoid_mesh():
     lam = lmax_scaled(*h30.matrix(0))
     assert h30.info(0)["omega"] * lam > 2.0
     check_power((32, 32, 64), 0.93)
+
+
+def test_breakdown_under_a_kept_hierarchy_sets_up_afresh():
+    """The 30 %-squashed 8x8x32 ARAP beam at the default margin: the hierarchy
+    and omega set up at iteration 0 (Sec. 4.2, 4.5) stop preconditioning A
+    at iteration 5 (the V-cycle is no longer positive definite and PCG breaks
+    down). With resetup_on_breakdown off the frame fails there; with it on
+    (the default) iteration 5 sets up afresh for its own A, and the hierarchy
+    it leaves is exactly the one a fresh setup of that A builds (aggregates,
+    transfer weights and every coarse matrix, bit for bit), and its solve
+    reaches the tolerance."""
+    w = W.arap_a0()
+    pos, vel = O.positions(w)
+    r0 = O.Sim(w, O.default_opts(resetup_on_breakdown=0)).step(pos, vel, 6)
+    assert r0["status"] == O.E_BREAKDOWN
+    assert r0["setup"].tolist() == [1, 0, 0, 0, 0, 0]
+    assert (r0["pcg_iters"][:5] > 0).all()
+    sim = O.Sim(w)
+    pos, vel = O.positions(w)
+    r = sim.step(pos, vel, 6)
+    assert r["status"] == 0
+    assert r["setup"].tolist() == [1, 0, 0, 0, 0, 2]
+    assert np.array_equal(r["pcg_iters"][:5], r0["pcg_iters"][:5])
+    assert np.array_equal(r["bnorm"], r0["bnorm"])
+    assert (r["ratio"] <= 1e-6).all()
+    # the last iteration set up afresh from its own A and was not refreshed since
+    rp, col = sim.pattern()
+    fresh = O.Hier.build(rp, col, sim.matrix_values())
+    kept = sim.hier()
+    assert kept.levels == fresh.levels
+    for l in range(kept.levels):
+        for a, b in zip(kept.matrix(l), fresh.matrix(l)):
+            assert np.array_equal(a, b)
+        if l + 1 < kept.levels:
+            for a, b in zip(kept.transfer(l), fresh.transfer(l)):
+                assert np.array_equal(a, b)
