@@ -241,7 +241,7 @@ void alloc_state(mgpbd_ctx *c) {
     S.mf = v;
     if (S.mixed()) {
       c->mf_pos32.alloc(nv4);
-      c->mf_gT32.alloc(ninc3);
+      c->mf_gT32.alloc(4 * (size_t)std::max<int64_t>((int64_t)c->vrow.n, 1));
       c->mf_u32.alloc(nv4);
       c->mf_alpha32.alloc(c->m);
       c->mf_w32.alloc(std::max<int64_t>(c->nv, 1));

@@ -33,10 +33,15 @@ __global__ void k_mf_incidence(int64_t n_inc, const int32_t *__restrict__ vrow,
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_inc) return;
   const double *g = grad + 12 * (int64_t)vrow[e] + 3 * vslot[e];
-  T *o = gT + 3 * e;
-  o[0] = (T)g[0];
-  o[1] = (T)g[1];
-  o[2] = (T)g[2];
+  if constexpr (sizeof(T) == 4) {
+    reinterpret_cast<float4 *>(gT)[e] =
+        make_float4((float)g[0], (float)g[1], (float)g[2], __int_as_float(vrow[e]));
+  } else {
+    T *o = gT + 3 * e;
+    o[0] = (T)g[0];
+    o[1] = (T)g[1];
+    o[2] = (T)g[2];
+  }
 }
 
 template <class T>
@@ -64,11 +69,19 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(const int *done, MfView<T>
     if (ok) {
       const int64_t a = A.vptr[v], b = A.vptr[v + 1];
       for (int64_t e = a + sub; e < b; e += G) {
-        const T xc = x(A.vrow[e]);
-        const T *g = A.gT + 3 * e;
-        sx += g[0] * xc;
-        sy += g[1] * xc;
-        sz += g[2] * xc;
+        if constexpr (sizeof(T) == 4) {
+          const float4 r = reinterpret_cast<const float4 *>(A.gT)[e];
+          const T xc = x(__float_as_int(r.w));
+          sx += r.x * xc;
+          sy += r.y * xc;
+          sz += r.z * xc;
+        } else {
+          const T xc = x(A.vrow[e]);
+          const T *g = A.gT + 3 * e;
+          sx += g[0] * xc;
+          sy += g[1] * xc;
+          sz += g[2] * xc;
+        }
       }
     }
     sx = group_sum<G, T>(sx);

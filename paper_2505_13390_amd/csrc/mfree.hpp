@@ -26,7 +26,9 @@ struct MfView {
   const T *alpha = nullptr;       // [m] alpha~ = alpha / dt^2
   const int64_t *vptr = nullptr;  // [nv + 1] incidence range of each vertex
   const int32_t *vrow = nullptr;  // [E] row of each incidence, ascending per vertex
-  const T *gT = nullptr;          // [E][3] gradient of each incidence
+  // gradient of each incidence: FP64 [E][3]; FP32 [E][4], the gradient and the
+  // incidence's row (its int32 bits in the fourth lane), one 16-byte load each
+  const T *gT = nullptr;
   const T *w = nullptr;           // [nv] inverse masses
   T *u = nullptr;                 // [nv][4] scratch of the vertex gather
   // rows whose gradients are read instead of recomputed (ARAP rows, whose
@@ -39,7 +41,7 @@ struct MfView {
 
 // Per global iteration, after the constraint kernel: positions as T
 // (pos[v] = (x, y, z)) and the per-incidence gradients gT[e] = the gradient
-// of slot vslot[e] of row vrow[e], converted to T.
+// of slot vslot[e] of row vrow[e], converted to T (FP32: with vrow[e] beside it).
 template <class T>
 void launch_mf_prepare(int64_t nv, const double *x, const double *y, const double *z,
                        int64_t n_inc, const int32_t *vrow, const int8_t *vslot,
