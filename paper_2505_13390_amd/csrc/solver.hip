@@ -1211,10 +1211,11 @@ void Solver::vcycle(int l, const T *r, T *z) {
   const MfView<T> *M = level_mf<T>(l);
   const CsrView<T> A = Buf<T>::A(L);
   const T *wd = Buf<T>::wdinv(L);
-  // On CSR levels the first two sweeps from zero are one pass that forms
-  // z1 = omega D^-1 r on the fly. A matrix-free level keeps the elementwise
-  // first sweep: its gather would fetch two vectors per incidence instead of
-  // one, which costs more than the separate kernel.
+  // The first Jacobi sweep from zero, z1 = omega D^-1 r, comes from the pass
+  // that produced r where it can: the restriction into a coarse level, the
+  // PCG update on a matrix-free fine level (first_ready). An assembled fine
+  // level forms the first two sweeps in one pass with z1 computed on the fly;
+  // otherwise z1 is an elementwise pass of its own.
   const bool from_restriction = first_from_restriction(l);
   const bool fuse = (M == nullptr) && opt.smoother == 0 && !from_restriction;
   const bool cheb = opt.smoother == 1;
