@@ -243,3 +243,29 @@ def test_arap_default_margin_sets_up_afresh_after_breakdown():
     assert e.value.status == B.E_BREAKDOWN
     assert np.array_equal(body.positions(), x0) and np.array_equal(body.velocities(), v0)
     body.close()
+
+
+def test_breakdown_in_a_batch_sets_up_the_whole_batch_again():
+    """A batch of the 30 %-squashed ARAP beam (which breaks down at the
+    default margin) and a small edge-and-volume beam (which does not): the
+    batch has one hierarchy, so the whole system is set up again at the
+    iteration where the ARAP body breaks down, every body reports setup_ran
+    2 there, and every solve of the frame still reaches 1e-6. The ARAP body
+    takes the same setup steps as when it is stepped alone."""
+    arap = W.arap_a0()
+    beam = W.beam(8, 3, 3, seed=5, volumes=True, alpha_edge=1e-8, alpha_vol=1e-9, dt=arap.dt)
+    assert tuple(beam.gravity) == tuple(arap.gravity)   # a batch shares dt and gravity
+    _, go = opts()
+    alone = B.Body(arap, go)
+    ra = alone.step(20)
+    alone.close()
+    batch = B.Batch([arap, beam], go)
+    res = batch.step(20)
+    flags = [r["setup_ran"].tolist() for r in res]
+    log("setup flags: ARAP alone %s, in the batch %s, beam in the batch %s"
+        % (ra["setup_ran"].tolist(), flags[0], flags[1]))
+    assert 2 in flags[0] and flags[0] == flags[1]
+    assert flags[0] == ra["setup_ran"].tolist()
+    for r in res:
+        assert (r["pcg_ratio"] <= 1e-6).all()
+    batch.close()
