@@ -28,11 +28,20 @@ __device__ __forceinline__ v4d mfma_tile_nt(const double *__restrict__ M, int64_
   return acc;
 }
 
-// One workgroup of 256 threads (4 waves). n is padded by the caller to a
+// One workgroup of kDenseThreads threads per matrix. n is padded by the caller to a
 // multiple of 16 with an identity block (the padding does not change the
 // inverse of the leading n x n part).
 // Factorisation + inverse by one workgroup; returns nonzero (in every thread)
 // when a pivot is not positive.
+// rows of a 16-column panel that the factorisation keeps in LDS (60 KB)
+constexpr int kPanelRows = 480;
+// threads of the workgroup that factorises and inverts one matrix: the
+// trailing updates and the product Z Z^T spread their 16 x 16 tiles over its
+// sixteen wavefronts
+constexpr int kDenseThreads = 1024;
+static_assert(kDenseThreads / kWave <= 16,
+              "the triangular inverse gives each wavefront a kPanelRows slice of the panel buffer");
+
 __device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
                                   double *__restrict__ Y, double *__restrict__ Ainv) {
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -41,28 +50,53 @@ __device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
   if (tid == 0) bad = 0;
   __syncthreads();
   // ---- blocked right-looking Cholesky, 16-column panels ----
+  // The panel (rows j0..np-1 of columns j0..j0+15) is factorised in LDS when
+  // it fits (its sixteen column steps are chains of barriers and dependent
+  // loads, which global memory makes slow), then written back for the
+  // trailing update; the arithmetic is the same either way.
+  __shared__ double panel[kPanelRows * 16];
+  const bool in_lds = np <= kPanelRows;
   for (int64_t j0 = 0; j0 < np; j0 += 16) {
+    double *Pb = in_lds ? panel : D + j0 * np + j0;   // element (i, k) at
+    const int64_t ps = in_lds ? 16 : np;               // Pb[(i - j0) ps + k - j0]
+    if (in_lds) {
+      __syncthreads();
+      for (int64_t idx = tid; idx < (np - j0) * 16; idx += nthr)
+        panel[idx] = D[(j0 + idx / 16) * np + j0 + idx % 16];
+    }
     // panel factorisation (columns j0..j0+15), scalar
     for (int64_t j = j0; j < j0 + 16; ++j) {
       __syncthreads();
+      double *pj = Pb + (j - j0) * ps + (j - j0);
       if (tid == 0) {
-        double d = D[j * np + j];
+        double d = *pj;
         if (!(d > 0.0)) bad = 1;
-        D[j * np + j] = sqrt(d > 0.0 ? d : 1.0);
+        *pj = sqrt(d > 0.0 ? d : 1.0);
       }
       __syncthreads();
       if (bad) break;
-      double ljj = D[j * np + j];
-      for (int64_t i = j + 1 + tid; i < np; i += nthr) D[i * np + j] = D[i * np + j] / ljj;
+      double ljj = *pj;
+      for (int64_t i = j + 1 + tid; i < np; i += nthr) {
+        double *e = Pb + (i - j0) * ps + (j - j0);
+        *e = *e / ljj;
+      }
       __syncthreads();
       // update the rest of the panel columns j+1..j0+15 for all rows below
       for (int64_t idx = tid; idx < (np - j - 1) * (j0 + 15 - j); idx += nthr) {
         int64_t w = j0 + 15 - j;
         int64_t i = j + 1 + idx / w, k = j + 1 + idx % w;
-        if (k <= i) D[i * np + k] = D[i * np + k] - D[i * np + j] * D[k * np + j];
+        if (k <= i) {
+          double *e = Pb + (i - j0) * ps + (k - j0);
+          *e = *e - Pb[(i - j0) * ps + (j - j0)] * Pb[(k - j0) * ps + (j - j0)];
+        }
       }
     }
     __syncthreads();
+    if (in_lds) {
+      for (int64_t idx = tid; idx < (np - j0) * 16; idx += nthr)
+        D[(j0 + idx / 16) * np + j0 + idx % 16] = panel[idx];
+      __syncthreads();
+    }
     if (bad) break;
     // trailing update with the FP64 matrix cores: tiles (ti, tk) below the
     // panel, tk <= ti, D[ti,tk] -= L[ti, panel] L[tk, panel]^T
@@ -87,30 +121,50 @@ __device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
   }
   __syncthreads();
   if (bad) return 1;
-  // ---- Y = L^-1 (lower): column c solved by one thread ----
-  for (int64_t c = tid; c < np; c += nthr) {
-    for (int64_t i = 0; i < c; ++i) Y[i * np + c] = 0.0;
-    for (int64_t i = c; i < np; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = c; k < i; ++k) s -= D[i * np + k] * Y[k * np + c];
-      Y[i * np + c] = s / D[i * np + i];
+  // ---- Z = (L^-1)^T: column c of L^-1 is stored as row c of Z ----
+  if (in_lds) {
+    // One wavefront per column: each substitution step's dot product is split
+    // over the 64 lanes (lane l owns the entries k = c + l mod 64, which it
+    // also keeps in this wave's slice of the now free panel buffer) and summed
+    // by a butterfly, so a column costs np - c short steps instead of one
+    // thread's (np - c)^2 / 2 dependent multiply-adds.
+    double *own = panel + wave * kPanelRows;
+    __syncthreads();
+    for (int64_t c = wave; c < np; c += nw) {
+      double *zc = Y + c * np;
+      for (int64_t i = lane; i < c; i += kWave) zc[i] = 0.0;
+      for (int64_t i = c; i < np; ++i) {
+        double s = 0.0;
+        for (int64_t k = c + lane; k < i; k += kWave) s += D[i * np + k] * own[k];
+        s = group_sum<kWave>(s);
+        const double zi = (((i == c) ? 1.0 : 0.0) - s) / D[i * np + i];
+        if (((i - c) & (kWave - 1)) == lane) {
+          own[i] = zi;
+          zc[i] = zi;
+        }
+      }
+    }
+  } else {
+    // thread c solves column c, walking its row of Z and row i of L
+    for (int64_t c = tid; c < np; c += nthr) {
+      double *zc = Y + c * np;
+      for (int64_t i = 0; i < c; ++i) zc[i] = 0.0;
+      for (int64_t i = c; i < np; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int64_t k = c; k < i; ++k) s -= D[i * np + k] * zc[k];
+        zc[i] = s / D[i * np + i];
+      }
     }
   }
   __syncthreads();
-  // ---- Ainv = Y^T Y on the matrix cores: Ainv[r][c] = sum_k Y[k][r] Y[k][c].
-  // Transpose Y into D (the factor is no longer needed) so both operands are
-  // read along rows: Ainv = Z Z^T with Z = Y^T.
-  for (int64_t idx = tid; idx < np * np; idx += nthr) {
-    int64_t i = idx / np, k = idx % np;
-    D[k * np + i] = Y[i * np + k];
-  }
-  __syncthreads();
+  // ---- Ainv = Z Z^T on the matrix cores: Ainv[r][c] = sum_k Z[r][k] Z[c][k],
+  // both operands read along rows of Z ----
   int64_t nt = np / 16;
   for (int64_t t = wave; t < nt * nt; t += nw) {
     int64_t ti = t / nt, tk = t % nt;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    int64_t kstart = (ti > tk ? ti : tk) * 16;   // Z[r][k] = Y[k][r] = 0 for k < r
-    acc = mfma_tile_nt(D, np, ti * 16, tk * 16, kstart, np - kstart, acc);
+    int64_t kstart = (ti > tk ? ti : tk) * 16;   // Z[r][k] = 0 for k < r
+    acc = mfma_tile_nt(Y, np, ti * 16, tk * 16, kstart, np - kstart, acc);
     const int cc = lane & 15, rb = lane >> 4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -147,7 +201,7 @@ __global__ void k_dense_scatter_batch(const DenseJob *jobs, const int64_t *__res
   }
 }
 
-__global__ __launch_bounds__(256) void k_chol_inverse_batch(const DenseJob *jobs, double *scratch,
+__global__ __launch_bounds__(kDenseThreads) void k_chol_inverse_batch(const DenseJob *jobs, double *scratch,
                                                             double *ainv, int *status) {
   const DenseJob j = jobs[blockIdx.x];
   const int64_t np = (j.n + 15) / 16 * 16;
@@ -164,7 +218,7 @@ void launch_dense_factor_batch(int njobs, const DenseJob *jobs, const int64_t *r
   dim3 g(64, njobs);
   k_dense_init_batch<<<g, kBlock, 0, s>>>(jobs, rp, col, val, scratch);
   k_dense_scatter_batch<<<g, kBlock, 0, s>>>(jobs, rp, col, val, scratch);
-  k_chol_inverse_batch<<<njobs, 256, 0, s>>>(jobs, scratch, ainv, status);
+  k_chol_inverse_batch<<<njobs, kDenseThreads, 0, s>>>(jobs, scratch, ainv, status);
 }
 
 

@@ -165,10 +165,14 @@ def test_c0_frame_with_forced_pcg_counts():
 def test_csr_pass_variants_match_oracle(tile, lanes):
     """Every CSR product variant the autotuner may pick (LDS stream tiles,
     lanes-per-row counts, SELL-C-sigma with tile -2) gives oracle parity on the
-    8x8x32 beam."""
+    8x8x32 beam. The GPU runs the oracle's PCG counts: this beam's solves end
+    on a residual plateau near 1e-6, where rounding-level differences move the
+    stopping iteration by up to 20 (e.g. 461 against 480), and the matrix of
+    the next iteration then differs by that solve's 1e-6 tolerance rather than
+    by rounding."""
     w = W.beam_c0()
-    sim, body, pos, vel, ores, gres = run_both(w, 3, spmv_tile=tile, spmv_lanes=lanes,
-                                               matrix_free=0)
+    sim, body, pos, vel, ores, gres = run_both(w, 3, force_from_oracle=True, spmv_tile=tile,
+                                               spmv_lanes=lanes, matrix_free=0)
     compare_hierarchy(sim, body, "tile %d lanes %d" % (tile, lanes), exact=False)
     err = rel_pos_err(body.positions(), pos)
     log("  position error %.3e iters %s %s" % (err, ores[0]["pcg_iters"].tolist(),
