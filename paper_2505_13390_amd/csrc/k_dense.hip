@@ -28,11 +28,6 @@ __device__ __forceinline__ v4d mfma_tile_nt(const double *__restrict__ M, int64_
   return acc;
 }
 
-// One workgroup of kDenseThreads threads per matrix. n is padded by the caller to a
-// multiple of 16 with an identity block (the padding does not change the
-// inverse of the leading n x n part).
-// Factorisation + inverse by one workgroup; returns nonzero (in every thread)
-// when a pivot is not positive.
 // rows of a 16-column panel that the factorisation keeps in LDS (60 KB)
 constexpr int kPanelRows = 480;
 // threads of the workgroup that factorises and inverts one matrix: the
@@ -42,6 +37,10 @@ constexpr int kDenseThreads = 1024;
 static_assert(kDenseThreads / kWave <= 16,
               "the triangular inverse gives each wavefront a kPanelRows slice of the panel buffer");
 
+// Factorisation + inverse of one matrix by one workgroup of kDenseThreads
+// threads; returns nonzero (in every thread) when a pivot is not positive.
+// n is padded by the caller to a multiple of 16 with an identity block (the
+// padding does not change the inverse of the leading n x n part).
 __device__ int chol_inverse_block(int64_t n, int64_t np, double *__restrict__ D,
                                   double *__restrict__ Y, double *__restrict__ Ainv) {
   const int tid = threadIdx.x, nthr = blockDim.x;
