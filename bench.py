@@ -32,6 +32,23 @@ METRIC = ("ms/frame and PCG constraint-DOF·iters/s at 1e-6 rel residual; "
 PEAK_HBM_GBS = 8000.0
 
 
+def batch_groups(sizes, limit: int = 2**31 - 1):
+    """Indices of consecutive bodies grouped so that each group's entries of A
+    (sizes[k] per body) sum to less than limit, the most a batch holds (its
+    entry indices are 32-bit); a body at or above limit alone forms a group
+    (the library then rejects it)."""
+    groups, cur, tot = [], [], 0
+    for k, n in enumerate(sizes):
+        if cur and tot + n >= limit:
+            groups.append(cur)
+            cur, tot = [], 0
+        cur.append(k)
+        tot += n
+    if cur:
+        groups.append(cur)
+    return groups
+
+
 def spmv_bytes(m: int, nnz: int) -> int:
     """Algorithmic bytes of one fine-level A p product (FP64 CSR, int32
     columns, int64 row pointers): values + columns + row pointers + one read
@@ -188,14 +205,7 @@ def bench_batch(args, B, W):
         # one system holds fewer than 2^31 entries of A: larger sets of bodies
         # (the eight stiff ellipsoid copies, 2.63e9 entries) run as the fewest
         # batches below that, one after another within each frame
-        groups, cur, tot = [], [], 0
-        for b in bodies:
-            if cur and tot + b.nnz >= 2**31 - 1:
-                groups.append(cur)
-                cur, tot = [], 0
-            cur.append(b)
-            tot += b.nnz
-        groups.append(cur)
+        groups = [[bodies[k] for k in g] for g in batch_groups([b.nnz for b in bodies])]
         handles = [B.mgpbd_batch_create([b.ctx for b in g]) for g in groups]
 
         def step():
