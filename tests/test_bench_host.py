@@ -34,3 +34,13 @@ def test_boundaries():
     assert bench.batch_groups([LIMIT - 1, 1]) == [[0], [1]]      # LIMIT would not fit
     assert bench.batch_groups([LIMIT - 2, 1]) == [[0, 1]]        # LIMIT - 1 fits
     assert bench.batch_groups([LIMIT + 5, 3]) == [[0], [1]]      # oversize alone
+
+
+def test_more_than_one_gpu_is_refused_before_any_gpu_work():
+    """the benchmark measures one GPU; --gpus 2 exits with a message and
+    status 2 without touching a device"""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
